@@ -1,0 +1,193 @@
+/*
+ * afps.h -- C ABI of the MI355X (gfx950) farthest-point-sampling library.
+ *
+ * Implements, as hand-written HIP kernels:
+ *   - plain farthest point sampling (FPS): Algorithm 1 of Li et al., "An
+ *     Adjustable Farthest Point Sampling Method for Approximately-sorted Point
+ *     Cloud Data" (arXiv 2208.08795);
+ *   - adjustable FPS (AFPS): the cloud is cut into M contiguous storage sectors
+ *     and each sector runs its own FPS, all sectors at once (Sec. III-B);
+ *   - nearest-point distance updating (NPDU): each iteration updates only the
+ *     distances of the new sample's storage neighbours (Sec. III-C), alone
+ *     (M = 1) or inside every AFPS sector.
+ *
+ * Common conventions
+ *   xyz      DEVICE pointer to n points, row-major fp32 (x, y, z per point,
+ *            12 bytes per point, 4-byte aligned).  Read only.
+ *   out_idx  DEVICE pointer to c int32 entries, written with indices into the
+ *            cloud (0 .. n-1): sector-major, and within a sector in pick order.
+ *   stream   a hipStream_t passed as void* (NULL = the default stream).  Every
+ *            call is asynchronous on that stream; results are valid once the
+ *            caller has synchronised it.
+ *   Ownership: the caller allocates and frees every buffer.  The single-cloud
+ *   calls allocate nothing; batch plans allocate host memory only (the device
+ *   side lives in the caller's workspace).
+ *   Arithmetic: squared Euclidean distance in fp32, ((dx*dx + dy*dy) + dz*dz),
+ *   no fused multiply-add; initial distance 1e10; argmax ties go to the lowest
+ *   index.  Results are bit-identical to a sequential evaluation of the paper's
+ *   loop in that arithmetic.
+ *   Preconditions not checked: coordinates finite, squared distances below
+ *   1e10 (coordinate extent below 1e5).
+ *   Errors: a negative status; nothing is launched and out_idx is untouched
+ *   when the arguments are rejected.  No C++ exception crosses this ABI.
+ *   Every function is thread-safe.
+ */
+#ifndef AFPS_H
+#define AFPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum afps_status {
+    AFPS_OK = 0,
+    AFPS_ERR_NULL = -1,        /* a required pointer is NULL */
+    AFPS_ERR_ARG = -2,         /* sizes violate 1 <= m <= c <= n, or a bad descriptor */
+    AFPS_ERR_RANGE = -3,       /* start outside [0, n) */
+    AFPS_ERR_WORKSPACE = -4,   /* workspace missing or smaller than required */
+    AFPS_ERR_HIP = -5,         /* a HIP runtime call failed; see afps_last_error() */
+    AFPS_ERR_UNSUPPORTED = -6, /* the problem exceeds what the kernels handle */
+    AFPS_ERR_DEVICE = -7       /* a kernel reported a failure (e.g. a timed-out grid barrier) */
+};
+
+/*
+ * Plain FPS, Algorithm 1: c samples from n points starting at index `start`.
+ * Requires 1 <= c <= n and 0 <= start < n.  Any n up to 2^31-1 that fits the
+ * device: clouds beyond one workgroup's register capacity are split across
+ * several workgroups that meet at a grid barrier each iteration.
+ */
+int afps_fps_plain(const float *xyz, int32_t n, int32_t c, int32_t start,
+                   int32_t *out_idx, void *stream);
+
+/*
+ * AFPS, Sec. III-B: M sectors of contiguous storage.  Sector s holds
+ * n_s = floor(n/m) + (s < n mod m) points starting at point
+ * b_s = s*floor(n/m) + min(s, n mod m), and takes c_s = floor(c/m) + (s < c mod m)
+ * samples written at out_idx[o_s ..], o_s = s*floor(c/m) + min(s, c mod m).
+ * Each sector starts at its local point (start mod n_s).
+ * Requires 1 <= m <= c <= n and 0 <= start < n.  m = 1 is plain FPS.
+ * Each sector must fit one workgroup: n_s <= afps_max_sector_points().
+ */
+int afps_afps(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t start,
+              int32_t *out_idx, void *stream);
+
+/*
+ * AFPS with NPDU, Sec. III-C: after each pick the distance update touches only
+ * the window [cur - floor(k/2), cur + ceil(k/2)] of the sector (the sample and
+ * its k storage neighbours), truncated at the sector's edges; there is no full
+ * first pass.  Requires k >= 0 plus the AFPS requirements.
+ */
+int afps_afps_npdu(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
+                   int32_t start, int32_t *out_idx, void *stream);
+
+/* Largest sector (points) a single workgroup holds in registers. */
+int32_t afps_max_sector_points(void);
+
+/* ---------------------------------------------------------------- batches */
+
+/*
+ * One cloud of a batch (ALG-5 of the paper's setting: many clouds per call,
+ * here of uneven size).  xyz_offset counts points into xyz_all, out_offset
+ * counts indices into out_all.  k < 0 turns NPDU off; m == 1 && k < 0 is plain
+ * FPS.  Indices written are local to the cloud (0 .. n-1).
+ */
+typedef struct afps_cloud_desc {
+    int64_t xyz_offset;
+    int64_t out_offset;
+    int32_t n, c, m, k;
+    int32_t start;
+    int32_t reserved;          /* must be 0 */
+} afps_cloud_desc;
+
+typedef struct afps_plan afps_plan;
+
+/*
+ * Build a batch plan on the host from `batch` HOST descriptors: validates
+ * them, expands every cloud into its sectors (work items), orders the items
+ * longest-first, groups them by kernel variant and sizes the workspace.
+ * Returns AFPS_OK and *plan, or an error (AFPS_ERR_ARG names the first bad
+ * descriptor in afps_last_error()).
+ */
+int afps_plan_create(const afps_cloud_desc *descs, int32_t batch, afps_plan **plan);
+
+/* Device workspace bytes the plan needs (work items + queue counters). */
+size_t afps_plan_workspace_bytes(const afps_plan *plan);
+
+/*
+ * Copy the plan's work-item table into `workspace` (DEVICE, >= the size
+ * above, 256-byte aligned) on `stream`.  Must precede afps_plan_launch with
+ * that workspace; the table stays valid until overwritten.
+ */
+int afps_plan_upload(afps_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Run the batch: reset the queue counters, then one persistent launch per
+ * kernel variant; each workgroup takes work items from a device queue with an
+ * atomic counter until the queue is empty.  Kernel launches only, so a
+ * caller may capture it in a hipGraph.
+ */
+int afps_plan_launch(const afps_plan *plan, const float *xyz_all, int32_t *out_all,
+                     void *workspace, void *stream);
+
+/*
+ * Same as afps_plan_launch, but the launch sequence is captured into a
+ * hipGraph the first time (per stream, buffers and workspace) and replayed
+ * afterwards.
+ */
+int afps_plan_graph_launch(afps_plan *plan, const float *xyz_all, int32_t *out_all,
+                           void *workspace, void *stream);
+
+/* Number of work items (sectors) and persistent launches of the plan. */
+int32_t afps_plan_items(const afps_plan *plan);
+int32_t afps_plan_launches(const afps_plan *plan);
+
+void afps_plan_destroy(afps_plan *plan);
+
+/*
+ * One-shot batch: plan, upload and launch.  descs are HOST descriptors;
+ * workspace must hold afps_batched_workspace_bytes(descs, batch) bytes.
+ */
+size_t afps_batched_workspace_bytes(const afps_cloud_desc *descs, int32_t batch);
+int afps_batched(const float *xyz_all, const afps_cloud_desc *descs, int32_t batch,
+                 int32_t *out_all, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------- tuning */
+
+/*
+ * Kernel variant chosen for a sector of n_s points (k < 0: no NPDU):
+ * waves per workgroup and point slots per thread.  Tuned entries override the
+ * built-in rule; afps_tune_set is what the autotuner calls.
+ */
+int afps_tune_get(int32_t n_s, int32_t k, int32_t *waves, int32_t *slots);
+int afps_tune_set(int32_t n_s_max, int32_t npdu, int32_t waves, int32_t slots);
+void afps_tune_reset(void);
+
+/*
+ * Run one sector variant explicitly (for the autotuner and tests): AFPS or
+ * NPDU over m sectors with the given waves / slots.  AFPS_ERR_UNSUPPORTED if
+ * that variant is not built or the sectors do not fit it.
+ */
+int afps_afps_variant(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
+                      int32_t start, int32_t *out_idx, int32_t waves, int32_t slots,
+                      void *stream);
+
+/*
+ * Bound on the polls of one grid-barrier wait in the multi-workgroup plain-FPS
+ * kernel (default 4M).  A wait that exceeds it marks the launch failed: every
+ * workgroup returns and the unfinished outputs hold -1.  Process-wide.
+ */
+int afps_set_spin_limit(uint32_t polls);
+
+/* --------------------------------------------------------------- status */
+
+const char *afps_status_string(int status);  /* static string */
+const char *afps_last_error(void);           /* this thread's last error detail */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFPS_H */

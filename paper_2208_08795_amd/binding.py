@@ -1,0 +1,261 @@
+"""Thin Python binding of libafps.so (include/afps.h): argument marshalling only.
+
+Every function takes torch tensors on a HIP device, checks dtype / device /
+shape / contiguity, and passes raw pointers and the current torch stream to
+the C ABI.  All sampling runs in the library's kernels; there is no other
+code path, and a missing library is an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libafps.so")
+
+_lock = threading.Lock()
+_lib = None
+
+
+class AfpsError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__("afps error %d (%s): %s" % (status, status_string(status), detail))
+        self.status = status
+
+
+class CloudDesc(ctypes.Structure):
+    _fields_ = [("xyz_offset", ctypes.c_int64), ("out_offset", ctypes.c_int64),
+                ("n", ctypes.c_int32), ("c", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def lib():
+    """Load libafps.so (built in-tree by the package's build step)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libafps.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        # torch carries its own HIP runtime with the same soname as the
+        # system one; loading torch first makes the library bind to that one
+        # runtime, so tensors' device pointers and torch streams are valid in
+        # both.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        i32, vp, sz = ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        sig = {
+            "afps_fps_plain": ([vp, i32, i32, i32, vp, vp], ctypes.c_int),
+            "afps_afps": ([vp, i32, i32, i32, i32, vp, vp], ctypes.c_int),
+            "afps_afps_npdu": ([vp, i32, i32, i32, i32, i32, vp, vp], ctypes.c_int),
+            "afps_afps_variant": ([vp, i32, i32, i32, i32, i32, vp, i32, i32, vp], ctypes.c_int),
+            "afps_max_sector_points": ([], i32),
+            "afps_plan_create": ([vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
+            "afps_plan_workspace_bytes": ([vp], sz),
+            "afps_plan_upload": ([vp, vp, sz, vp], ctypes.c_int),
+            "afps_plan_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
+            "afps_plan_graph_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
+            "afps_plan_items": ([vp], i32),
+            "afps_plan_launches": ([vp], i32),
+            "afps_plan_destroy": ([vp], None),
+            "afps_batched_workspace_bytes": ([vp, i32], sz),
+            "afps_batched": ([vp, vp, i32, vp, vp, sz, vp], ctypes.c_int),
+            "afps_tune_get": ([i32, i32, i32p, i32p], ctypes.c_int),
+            "afps_tune_set": ([i32, i32, i32, i32], ctypes.c_int),
+            "afps_tune_reset": ([], None),
+            "afps_set_spin_limit": ([ctypes.c_uint32], ctypes.c_int),
+            "afps_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "afps_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+        return L
+
+
+def status_string(status: int) -> str:
+    return lib().afps_status_string(status).decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise AfpsError(status, lib().afps_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_points(xyz):
+    torch = _torch()
+    if not isinstance(xyz, torch.Tensor) or xyz.device.type != "cuda":
+        raise TypeError("xyz must be a torch tensor on a HIP device")
+    if xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+        raise TypeError("xyz must be a contiguous float32 (N, 3) tensor")
+
+
+def _out(xyz, c, out):
+    torch = _torch()
+    if out is None:
+        return torch.empty(c, dtype=torch.int32, device=xyz.device)
+    if out.dtype != torch.int32 or out.device != xyz.device or not out.is_contiguous() or out.numel() < c:
+        raise TypeError("out must be a contiguous int32 tensor of >= c entries on xyz's device")
+    return out
+
+
+def fps(xyz, c: int, start: int = 0, out=None, stream=None):
+    """Plain FPS (Algorithm 1) -> int32 indices."""
+    _check_points(xyz)
+    out = _out(xyz, c, out)
+    _check(lib().afps_fps_plain(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, start,
+                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def afps(xyz, c: int, m: int, start: int = 0, out=None, stream=None, variant=None):
+    """AFPS with m sectors (Sec. III-B) -> int32 indices, sector-major.
+
+    ``variant=(waves, slots)`` forces a kernel variant (autotuner, tests).
+    """
+    _check_points(xyz)
+    out = _out(xyz, c, out)
+    if variant is None:
+        rc = lib().afps_afps(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, start,
+                             ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    else:
+        rc = lib().afps_afps_variant(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, -1, start,
+                                     ctypes.c_void_p(out.data_ptr()), variant[0], variant[1],
+                                     _stream_handle(stream))
+    _check(rc)
+    return out
+
+
+def afps_npdu(xyz, c: int, m: int, k: int, start: int = 0, out=None, stream=None, variant=None):
+    """AFPS with NPDU window k (Sec. III-C) -> int32 indices, sector-major."""
+    _check_points(xyz)
+    out = _out(xyz, c, out)
+    if variant is None:
+        rc = lib().afps_afps_npdu(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, k, start,
+                                  ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    else:
+        rc = lib().afps_afps_variant(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, k, start,
+                                     ctypes.c_void_p(out.data_ptr()), variant[0], variant[1],
+                                     _stream_handle(stream))
+    _check(rc)
+    return out
+
+
+def descriptors(sizes, cs, ms, ks, starts):
+    """Host descriptor array for clouds packed back to back (points and outputs)."""
+    n = len(sizes)
+    arr = (CloudDesc * n)()
+    xo = oo = 0
+    for i in range(n):
+        arr[i] = CloudDesc(xo, oo, int(sizes[i]), int(cs[i]), int(ms[i]),
+                           -1 if ks[i] is None else int(ks[i]), int(starts[i]), 0)
+        xo += int(sizes[i])
+        oo += int(cs[i])
+    return arr, xo, oo
+
+
+class BatchPlan:
+    """A batch of clouds packed back to back in one (sum N, 3) tensor.
+
+    Owns the device workspace (a torch tensor) and the library's plan.
+    """
+
+    def __init__(self, sizes, cs, ms, ks, starts, device="cuda"):
+        torch = _torch()
+        self.descs, self.total_points, self.total_samples = descriptors(sizes, cs, ms, ks, starts)
+        h = ctypes.c_void_p()
+        _check(lib().afps_plan_create(ctypes.cast(self.descs, ctypes.c_void_p), len(sizes), ctypes.byref(h)))
+        self._plan = h
+        self.workspace_bytes = int(lib().afps_plan_workspace_bytes(h))
+        self.items = int(lib().afps_plan_items(h))
+        self.launches = int(lib().afps_plan_launches(h))
+        self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
+        self.offsets = [d.out_offset for d in self.descs]
+        self._uploaded = False
+
+    def upload(self, stream=None):
+        _check(lib().afps_plan_upload(self._plan, ctypes.c_void_p(self.workspace.data_ptr()),
+                                      self.workspace.numel(), _stream_handle(stream)))
+        self._uploaded = True
+
+    def _args(self, xyz_all, out_all):
+        _check_points(xyz_all)
+        if xyz_all.shape[0] < self.total_points:
+            raise ValueError("xyz_all holds fewer points than the plan's clouds")
+        out_all = _out(xyz_all, self.total_samples, out_all)
+        if not self._uploaded:
+            self.upload()
+        return out_all
+
+    def launch(self, xyz_all, out_all=None, stream=None, graph=False):
+        out_all = self._args(xyz_all, out_all)
+        f = lib().afps_plan_graph_launch if graph else lib().afps_plan_launch
+        _check(f(self._plan, ctypes.c_void_p(xyz_all.data_ptr()), ctypes.c_void_p(out_all.data_ptr()),
+                 ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(stream)))
+        return out_all
+
+    def split(self, out_all):
+        """Per-cloud views of the packed output."""
+        return [out_all[self.descs[i].out_offset:self.descs[i].out_offset + self.descs[i].c]
+                for i in range(len(self.descs))]
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            lib().afps_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batched(clouds, cs, ms, ks, starts=None, graph=False, stream=None):
+    """Sample a list of (N_i, 3) device tensors in one batch; returns per-cloud indices."""
+    torch = _torch()
+    starts = starts or [0] * len(clouds)
+    plan = BatchPlan([c.shape[0] for c in clouds], cs, ms, ks, starts, device=clouds[0].device)
+    xyz_all = torch.cat(list(clouds), dim=0).contiguous()
+    out = plan.launch(xyz_all, stream=stream, graph=graph)
+    res = [o.clone() for o in plan.split(out)]
+    torch.cuda.current_stream().synchronize()
+    plan.close()
+    return res
+
+
+def set_spin_limit(polls: int):
+    _check(lib().afps_set_spin_limit(polls))
+
+
+def tune_get(n_s: int, k=None):
+    w, s = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().afps_tune_get(n_s, -1 if k is None else k, ctypes.byref(w), ctypes.byref(s)))
+    return w.value, s.value
+
+
+def tune_set(n_s_max: int, waves: int, slots: int):
+    _check(lib().afps_tune_set(n_s_max, 0, waves, slots))
+
+
+def tune_reset():
+    lib().afps_tune_reset()

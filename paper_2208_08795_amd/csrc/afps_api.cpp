@@ -1,0 +1,689 @@
+// Host side of the C ABI declared in include/afps.h.
+//
+// Responsibilities: argument validation (before anything touches the GPU),
+// the sector plan of Sec. III-B, the choice of kernel variant per sector size
+// (built-in rule or tuned override), launches on the caller's stream, batch
+// plans (work-item tables for the persistent kernels, per-variant buckets on
+// helper streams, optional hipGraph capture/replay) and the grid-barrier pool
+// of the multi-workgroup plain-FPS kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "afps.h"
+#include "variants.hpp"
+
+using namespace afps;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return AFPS_ERR_HIP;
+}
+
+#define AFPS_HIP(call)                                    \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------------ variants
+
+struct Registry {
+    std::vector<VariantEntry> full;   // full-update sector kernels
+    std::vector<NpduEntry> npdu;      // NPDU sector kernels, ascending capacity
+    std::vector<GridVariant> grid;    // multi-workgroup plain FPS
+    Registry() {
+        register_variants_w1(full);
+        register_variants_w2(full);
+        register_variants_w4(full);
+        register_variants_w8(full);
+        register_variants_w16(full);
+        register_npdu_variants(npdu);
+        register_grid_variants(grid);
+    }
+};
+
+Registry& registry() {
+    static Registry r;
+    return r;
+}
+
+const VariantEntry* find_full(int waves, int slots) {
+    for (const auto& v : registry().full)
+        if (v.waves == waves && v.slots == slots) return &v;
+    return nullptr;
+}
+
+int capacity(const VariantEntry& v) { return 64 * v.waves * v.slots; }
+int capacity(const NpduEntry& v) { return 64 * 64 * v.chunk64; }
+
+constexpr int kMaxFullSector = 32768;   // W = 16, P = 32 with distances in LDS
+
+// Built-in rule for a full-update sector of n points: about 512 points per
+// wave (a power of two number of waves, at most 16), then the smallest slot
+// count that holds the sector.
+const VariantEntry* rule_full(int n) {
+    int waves = 1;
+    while (waves < 16 && waves * 512 < n) waves *= 2;
+    const VariantEntry* best = nullptr;
+    for (const auto& v : registry().full)
+        if (v.waves == waves && capacity(v) >= n && (!best || v.slots < best->slots)) best = &v;
+    if (!best)   // fall back to any variant that holds it, fewest slots first
+        for (const auto& v : registry().full)
+            if (capacity(v) >= n && (!best || capacity(v) < capacity(*best))) best = &v;
+    return best;
+}
+
+struct Tuned {
+    int n_max, waves, slots;
+};
+std::mutex g_tune_mu;
+std::vector<Tuned> g_tuned;   // ascending n_max
+bool g_tune_loaded = false;
+
+void load_tune_file_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("AFPS_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char kind[16];
+    int n_max, waves, slots;
+    while (std::fscanf(f, "%15s %d %d %d", kind, &n_max, &waves, &slots) == 4) {
+        if (std::strcmp(kind, "full") != 0) continue;
+        const VariantEntry* v = find_full(waves, slots);
+        if (v && capacity(*v) >= n_max) g_tuned.push_back({n_max, waves, slots});
+    }
+    std::fclose(f);
+    std::sort(g_tuned.begin(), g_tuned.end(),
+              [](const Tuned& a, const Tuned& b) { return a.n_max < b.n_max; });
+}
+
+const VariantEntry* choose_full(int n) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file_locked();
+        for (const auto& t : g_tuned)
+            if (n <= t.n_max) {
+                const VariantEntry* v = find_full(t.waves, t.slots);
+                if (v && capacity(*v) >= n) return v;
+                break;
+            }
+    }
+    return rule_full(n);
+}
+
+const NpduEntry* choose_npdu(int n) {
+    for (const auto& v : registry().npdu)
+        if (capacity(v) >= n) return &v;
+    return nullptr;
+}
+
+int npdu_lds_bytes(const NpduEntry& v, int n) { return (v.xyz_in_lds ? 16 : 4) * n; }
+
+// ------------------------------------------------------------ devices
+
+struct DeviceState {
+    bool ready = false;
+    int cu_count = 0;
+    size_t max_lds = 0;
+    std::vector<hipStream_t> helpers;        // bucket streams for batch plans
+    void* grid_pool = nullptr;               // grid-barrier blocks
+    std::vector<hipEvent_t> grid_events;     // last user of each block
+    int grid_next = 0;
+};
+
+constexpr int kHelperStreams = 4;
+constexpr int kGridBlocks = 16;
+
+std::mutex g_dev_mu;
+std::map<int, DeviceState> g_devices;
+
+int device_state(DeviceState** out) {
+    int dev = 0;
+    AFPS_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceState& d = g_devices[dev];
+    if (!d.ready) {
+        int cus = 0, lds = 0;
+        AFPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        AFPS_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        d.cu_count = cus;
+        d.max_lds = (size_t)lds;
+        // Kernels that take more than the default dynamic LDS.
+        for (const auto& v : registry().full)
+            if (v.lds_bytes > 0) {
+                (void)hipFuncSetAttribute(v.direct, hipFuncAttributeMaxDynamicSharedMemorySize, v.lds_bytes);
+                (void)hipFuncSetAttribute(v.persistent, hipFuncAttributeMaxDynamicSharedMemorySize, v.lds_bytes);
+            }
+        for (const auto& v : registry().npdu) {
+            const int b = npdu_lds_bytes(v, capacity(v));
+            (void)hipFuncSetAttribute(v.direct, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+            (void)hipFuncSetAttribute(v.persistent, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        }
+        (void)hipGetLastError();
+        d.ready = true;
+    }
+    *out = &d;
+    return AFPS_OK;
+}
+
+int helper_streams(DeviceState* d) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    while ((int)d->helpers.size() < kHelperStreams) {
+        hipStream_t s;
+        AFPS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        d->helpers.push_back(s);
+    }
+    return AFPS_OK;
+}
+
+// ------------------------------------------------------------ validation
+
+int check_sizes(int32_t n, int32_t c, int32_t m, int32_t start) {
+    if (m < 1 || c < m || n < c)
+        return fail(AFPS_ERR_ARG, "sizes must satisfy 1 <= m <= c <= n (n=" + std::to_string(n) +
+                                      ", c=" + std::to_string(c) + ", m=" + std::to_string(m) + ")");
+    if (start < 0 || start >= n)
+        return fail(AFPS_ERR_RANGE, "start " + std::to_string(start) + " outside [0, n)");
+    return AFPS_OK;
+}
+
+int32_t largest_sector(int32_t n, int32_t m) { return n / m + (n % m ? 1 : 0); }
+
+// Windows wider than twice the sector behave exactly like 2*n_s (the window
+// then spans the sector from any sample); clamping keeps index sums in range.
+int32_t clamp_k(int32_t k, int32_t n_s) { return k > 2 * n_s ? 2 * n_s : k; }
+
+// ------------------------------------------------------------ launches
+
+int launch_full_direct(const VariantEntry& v, const float* xyz, int32_t n, int32_t c, int32_t m,
+                       int32_t start, int32_t* out, hipStream_t stream) {
+    void* args[] = {(void*)&xyz, (void*)&n, (void*)&c, (void*)&m, (void*)&start, (void*)&out};
+    AFPS_HIP(hipLaunchKernel(v.direct, dim3(m), dim3(64 * v.waves), args, v.lds_bytes, stream));
+    return AFPS_OK;
+}
+
+int launch_npdu_direct(const NpduEntry& v, const float* xyz, int32_t n, int32_t c, int32_t m,
+                       int32_t k, int32_t start, int32_t* out, hipStream_t stream) {
+    const int lds = npdu_lds_bytes(v, largest_sector(n, m));
+    void* args[] = {(void*)&xyz, (void*)&n, (void*)&c, (void*)&m, (void*)&k, (void*)&start, (void*)&out};
+    AFPS_HIP(hipLaunchKernel(v.direct, dim3(m), dim3(64), args, lds, stream));
+    return AFPS_OK;
+}
+
+unsigned g_spin_limit = 1u << 22;
+
+int launch_grid_fps(const float* xyz, int32_t n, int32_t c, int32_t start, int32_t* out,
+                     hipStream_t stream) {
+    const GridVariant* gv = nullptr;
+    int groups = 0;
+    // About 8192 points per workgroup; wider blocks once 64 workgroups are not enough.
+    for (const auto& v : registry().grid) {
+        const int chunk = 64 * v.waves * v.slots;
+        const int g = (int)(((int64_t)n + chunk - 1) / chunk);
+        if (v.slots >= 8 && g <= kMaxGridGroups) { gv = &v; groups = g; break; }
+    }
+    if (!gv)
+        return fail(AFPS_ERR_UNSUPPORTED, "cloud of " + std::to_string(n) +
+                                              " points exceeds the multi-workgroup FPS capacity");
+    // Balance the blocks (the last one is not nearly empty); recount so that
+    // every workgroup owns at least one point.
+    const int32_t chunk = (int32_t)(((int64_t)n + groups - 1) / groups);
+    groups = (int)(((int64_t)n + chunk - 1) / chunk);
+    DeviceState* d;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    void* block;
+    hipEvent_t ev;
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        if (!d->grid_pool) {
+            AFPS_HIP(hipMalloc(&d->grid_pool, (size_t)kGridBlocks * kGridSyncBytes));
+            for (int i = 0; i < kGridBlocks; ++i) {
+                hipEvent_t e;
+                AFPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                d->grid_events.push_back(e);
+            }
+        }
+        const int slot = d->grid_next;
+        d->grid_next = (slot + 1) % kGridBlocks;
+        block = (char*)d->grid_pool + (size_t)slot * kGridSyncBytes;
+        ev = d->grid_events[slot];
+        // The block's previous user (possibly on another stream) must be done.
+        AFPS_HIP(hipStreamWaitEvent(stream, ev, 0));
+        void* rargs[] = {&block};
+        AFPS_HIP(hipLaunchKernel(grid_reset_kernel(), dim3(1), dim3(64), rargs, 0, stream));
+        unsigned spin = g_spin_limit;
+        void* args[] = {(void*)&xyz, (void*)&n, (void*)&c, (void*)&start, (void*)&chunk,
+                        (void*)&out, &block, &spin};
+        AFPS_HIP(hipLaunchCooperativeKernel(gv->kernel, dim3(groups), dim3(64 * gv->waves), args, 0,
+                                            stream));
+        AFPS_HIP(hipEventRecord(ev, stream));
+    }
+    return AFPS_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char* afps_status_string(int status) {
+    switch (status) {
+        case AFPS_OK: return "ok";
+        case AFPS_ERR_NULL: return "null pointer argument";
+        case AFPS_ERR_ARG: return "invalid size arguments";
+        case AFPS_ERR_RANGE: return "start index out of range";
+        case AFPS_ERR_WORKSPACE: return "workspace missing or too small";
+        case AFPS_ERR_HIP: return "HIP runtime error";
+        case AFPS_ERR_UNSUPPORTED: return "problem exceeds the kernels' capacity";
+        case AFPS_ERR_DEVICE: return "device-side failure";
+        default: return "unknown status";
+    }
+}
+
+const char* afps_last_error(void) { return g_last_error.c_str(); }
+
+int32_t afps_max_sector_points(void) { return kMaxFullSector; }
+
+int afps_afps(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t start, int32_t* out_idx,
+              void* stream) {
+    if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
+    int rc = check_sizes(n, c, m, start);
+    if (rc) return rc;
+    const int32_t ns = largest_sector(n, m);
+    if (ns > kMaxFullSector) {
+        if (m == 1) return afps_fps_plain(xyz, n, c, start, out_idx, stream);
+        return fail(AFPS_ERR_UNSUPPORTED, "sector of " + std::to_string(ns) +
+                                              " points exceeds one workgroup (use more sectors)");
+    }
+    DeviceState* d;
+    if ((rc = device_state(&d))) return rc;
+    const VariantEntry* v = choose_full(ns);
+    if (!v) return fail(AFPS_ERR_UNSUPPORTED, "no kernel variant holds the sector");
+    return launch_full_direct(*v, xyz, n, c, m, start, out_idx, (hipStream_t)stream);
+}
+
+int afps_afps_npdu(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
+                   int32_t* out_idx, void* stream) {
+    if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
+    int rc = check_sizes(n, c, m, start);
+    if (rc) return rc;
+    if (k < 0) return fail(AFPS_ERR_ARG, "NPDU needs k >= 0");
+    const int32_t ns = largest_sector(n, m);
+    const NpduEntry* v = choose_npdu(ns);
+    if (!v)
+        return fail(AFPS_ERR_UNSUPPORTED, "NPDU sector of " + std::to_string(ns) +
+                                              " points exceeds one workgroup (use more sectors)");
+    DeviceState* d;
+    if ((rc = device_state(&d))) return rc;
+    return launch_npdu_direct(*v, xyz, n, c, m, clamp_k(k, ns), start, out_idx, (hipStream_t)stream);
+}
+
+int afps_fps_plain(const float* xyz, int32_t n, int32_t c, int32_t start, int32_t* out_idx,
+                   void* stream) {
+    if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
+    int rc = check_sizes(n, c, 1, start);
+    if (rc) return rc;
+    if (n <= kMaxFullSector) return afps_afps(xyz, n, c, 1, start, out_idx, stream);
+    return launch_grid_fps(xyz, n, c, start, out_idx, (hipStream_t)stream);
+}
+
+int afps_afps_variant(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
+                      int32_t* out_idx, int32_t waves, int32_t slots, void* stream) {
+    if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
+    int rc = check_sizes(n, c, m, start);
+    if (rc) return rc;
+    const int32_t ns = largest_sector(n, m);
+    DeviceState* d;
+    if ((rc = device_state(&d))) return rc;
+    if (k >= 0) {
+        // NPDU: `slots` selects the chunk size in units of 64 points.
+        for (const auto& v : registry().npdu)
+            if (v.chunk64 == slots && capacity(v) >= ns && waves == 1)
+                return launch_npdu_direct(v, xyz, n, c, m, clamp_k(k, ns), start, out_idx,
+                                          (hipStream_t)stream);
+        return fail(AFPS_ERR_UNSUPPORTED, "no such NPDU variant for this sector size");
+    }
+    const VariantEntry* v = find_full(waves, slots);
+    if (!v || capacity(*v) < ns) return fail(AFPS_ERR_UNSUPPORTED, "no such variant for this sector size");
+    return launch_full_direct(*v, xyz, n, c, m, start, out_idx, (hipStream_t)stream);
+}
+
+int afps_tune_get(int32_t n_s, int32_t k, int32_t* waves, int32_t* slots) {
+    if (!waves || !slots) return fail(AFPS_ERR_NULL, "waves and slots must be non-null");
+    if (n_s < 1) return fail(AFPS_ERR_ARG, "n_s must be positive");
+    if (k >= 0) {
+        const NpduEntry* v = choose_npdu(n_s);
+        if (!v) return fail(AFPS_ERR_UNSUPPORTED, "sector too large");
+        *waves = 1;
+        *slots = v->chunk64;
+        return AFPS_OK;
+    }
+    const VariantEntry* v = n_s <= kMaxFullSector ? choose_full(n_s) : nullptr;
+    if (!v) return fail(AFPS_ERR_UNSUPPORTED, "sector too large");
+    *waves = v->waves;
+    *slots = v->slots;
+    return AFPS_OK;
+}
+
+int afps_tune_set(int32_t n_s_max, int32_t npdu, int32_t waves, int32_t slots) {
+    if (npdu) return fail(AFPS_ERR_ARG, "NPDU variants are chosen by sector size only");
+    const VariantEntry* v = find_full(waves, slots);
+    if (!v || capacity(*v) < n_s_max) return fail(AFPS_ERR_ARG, "variant does not exist or is too small");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
+    g_tuned.erase(std::remove_if(g_tuned.begin(), g_tuned.end(),
+                                 [&](const Tuned& t) { return t.n_max == n_s_max; }),
+                  g_tuned.end());
+    g_tuned.push_back({n_s_max, waves, slots});
+    std::sort(g_tuned.begin(), g_tuned.end(),
+              [](const Tuned& a, const Tuned& b) { return a.n_max < b.n_max; });
+    return AFPS_OK;
+}
+
+void afps_tune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+    g_tune_loaded = true;   // forget the cache file too
+}
+
+int afps_set_spin_limit(uint32_t polls) {
+    if (polls == 0) return fail(AFPS_ERR_ARG, "spin limit must be positive");
+    g_spin_limit = polls;
+    return AFPS_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ batch plans
+
+namespace {
+
+struct Bucket {
+    const void* kernel;   // persistent kernel
+    int block;            // threads per workgroup
+    int lds_bytes;        // dynamic LDS
+    int first, count;     // items [first, first + count) of the plan
+    int grid;             // workgroups launched
+    double cost;          // estimated work, for ordering
+};
+
+constexpr size_t kCounterBytes = 256;   // queue counters, one per bucket
+constexpr int kMaxBuckets = (int)(kCounterBytes / sizeof(unsigned));
+
+}  // namespace
+
+struct afps_plan {
+    std::vector<WorkItem> items;
+    std::vector<Bucket> buckets;
+    size_t ws_bytes = 0;
+    int device = 0;
+    std::vector<hipEvent_t> events;   // fork / join events (1 + helper streams)
+    std::mutex mu;
+    hipGraphExec_t exec = nullptr;
+    const void* g_xyz = nullptr;
+    void* g_out = nullptr;
+    void* g_ws = nullptr;
+    hipStream_t capture = nullptr;   // stream the graph is captured on
+    ~afps_plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (capture) (void)hipStreamDestroy(capture);
+        for (auto e : events) (void)hipEventDestroy(e);
+    }
+};
+
+extern "C" {
+
+int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** plan_out) {
+    if (!plan_out || (!descs && batch > 0)) return fail(AFPS_ERR_NULL, "descs and plan must be non-null");
+    *plan_out = nullptr;
+    if (batch < 0) return fail(AFPS_ERR_ARG, "batch must be >= 0");
+    std::unique_ptr<afps_plan> plan(new afps_plan());
+
+    struct Staged {
+        WorkItem item;
+        const void* kernel;
+        int block, lds;
+        double cost;
+    };
+    std::vector<Staged> staged;
+    for (int32_t b = 0; b < batch; ++b) {
+        const afps_cloud_desc& d = descs[b];
+        const std::string where = "descriptor " + std::to_string(b) + ": ";
+        if (d.reserved != 0 || d.xyz_offset < 0 || d.out_offset < 0)
+            return fail(AFPS_ERR_ARG, where + "negative offset or nonzero reserved field");
+        int rc = check_sizes(d.n, d.c, d.m, d.start);
+        if (rc) return fail(rc, where + g_last_error);
+        const int32_t qn = d.n / d.m, rn = d.n % d.m, qc = d.c / d.m, rc_ = d.c % d.m;
+        for (int32_t s = 0; s < d.m; ++s) {
+            Staged st;
+            WorkItem& it = st.item;
+            const int32_t ns = qn + (s < rn ? 1 : 0), bs = s * qn + std::min(s, rn);
+            const int32_t cs = qc + (s < rc_ ? 1 : 0), os = s * qc + std::min(s, rc_);
+            it.xyz_offset = d.xyz_offset + bs;
+            it.out_offset = d.out_offset + os;
+            it.n = ns;
+            it.c = cs;
+            it.k = d.k < 0 ? -1 : clamp_k(d.k, ns);
+            it.start = d.start % ns;
+            it.base = bs;
+            it.pad = 0;
+            if (d.k >= 0) {
+                const NpduEntry* v = choose_npdu(ns);
+                if (!v) return fail(AFPS_ERR_UNSUPPORTED, where + "NPDU sector too large");
+                st.kernel = v->persistent;
+                st.block = 64;
+                st.lds = npdu_lds_bytes(*v, ns);
+                st.cost = (double)cs * 300.0;   // per-iteration cost roughly independent of n_s
+            } else {
+                const VariantEntry* v = ns <= kMaxFullSector ? choose_full(ns) : nullptr;
+                if (!v)
+                    return fail(AFPS_ERR_UNSUPPORTED,
+                                where + "sector of " + std::to_string(ns) +
+                                    " points exceeds one workgroup (split into more sectors)");
+                st.kernel = v->persistent;
+                st.block = 64 * v->waves;
+                st.lds = v->lds_bytes;
+                st.cost = (double)cs * (double)ns / 64.0 + (double)cs * 100.0;
+            }
+            staged.push_back(st);
+        }
+    }
+    // Group by kernel; inside a group, longest first.
+    std::stable_sort(staged.begin(), staged.end(), [](const Staged& a, const Staged& b) {
+        if (a.kernel != b.kernel) return a.kernel < b.kernel;
+        return a.cost > b.cost;
+    });
+    for (size_t i = 0; i < staged.size();) {
+        size_t j = i;
+        Bucket bk{staged[i].kernel, staged[i].block, 0, (int)i, 0, 0, 0.0};
+        while (j < staged.size() && staged[j].kernel == bk.kernel) {
+            bk.lds_bytes = std::max(bk.lds_bytes, staged[j].lds);
+            bk.cost += staged[j].cost;
+            ++j;
+        }
+        bk.count = (int)(j - i);
+        plan->buckets.push_back(bk);
+        i = j;
+    }
+    if ((int)plan->buckets.size() > kMaxBuckets) return fail(AFPS_ERR_UNSUPPORTED, "too many kernel variants in one plan");
+    // Largest bucket first: it gets the first helper stream.
+    std::sort(plan->buckets.begin(), plan->buckets.end(),
+              [](const Bucket& a, const Bucket& b) { return a.cost > b.cost; });
+    plan->items.reserve(staged.size());
+    {
+        std::vector<WorkItem> ordered(staged.size());
+        int pos = 0;
+        for (auto& bk : plan->buckets) {
+            for (int i = 0; i < bk.count; ++i) ordered[pos + i] = staged[bk.first + i].item;
+            bk.first = pos;
+            pos += bk.count;
+        }
+        plan->items.swap(ordered);
+    }
+    // Persistent grid: as many workgroups as stay resident, at most one per item.
+    if (!plan->buckets.empty()) {
+        DeviceState* ds;
+        int rc = device_state(&ds);
+        if (rc) return rc;
+        AFPS_HIP(hipGetDevice(&plan->device));
+        for (auto& bk : plan->buckets) {
+            int per_cu = 0;
+            AFPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bk.kernel, bk.block, bk.lds_bytes));
+            if (per_cu < 1) return fail(AFPS_ERR_UNSUPPORTED, "a kernel variant cannot be resident");
+            bk.grid = std::min(bk.count, per_cu * ds->cu_count);
+        }
+        if (plan->buckets.size() > 1) {
+            int hrc = helper_streams(ds);   // created outside any stream capture
+            if (hrc) return hrc;
+        }
+        const int n_events = 1 + kHelperStreams;
+        for (int i = 0; i < n_events; ++i) {
+            hipEvent_t e;
+            AFPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            plan->events.push_back(e);
+        }
+    }
+    plan->ws_bytes = kCounterBytes + plan->items.size() * sizeof(WorkItem);
+    plan->ws_bytes = (plan->ws_bytes + 255) / 256 * 256;
+    *plan_out = plan.release();
+    return AFPS_OK;
+}
+
+size_t afps_plan_workspace_bytes(const afps_plan* plan) { return plan ? plan->ws_bytes : 0; }
+int32_t afps_plan_items(const afps_plan* plan) { return plan ? (int32_t)plan->items.size() : 0; }
+int32_t afps_plan_launches(const afps_plan* plan) { return plan ? (int32_t)plan->buckets.size() : 0; }
+
+void afps_plan_destroy(afps_plan* plan) { delete plan; }
+
+int afps_plan_upload(afps_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
+    if (plan->items.empty()) return AFPS_OK;
+    if (!workspace || workspace_bytes < plan->ws_bytes)
+        return fail(AFPS_ERR_WORKSPACE, "workspace needs " + std::to_string(plan->ws_bytes) + " bytes");
+    if (((uintptr_t)workspace & 255) != 0) return fail(AFPS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    // Pageable source: the copy has consumed the host table when this returns.
+    AFPS_HIP(hipMemcpyAsync((char*)workspace + kCounterBytes, plan->items.data(),
+                            plan->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                            (hipStream_t)stream));
+    return AFPS_OK;
+}
+
+int afps_plan_launch(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
+                     void* stream_) {
+    if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
+    if (plan->items.empty()) return AFPS_OK;
+    if (!xyz_all || !out_all) return fail(AFPS_ERR_NULL, "xyz_all and out_all must be non-null");
+    if (!workspace) return fail(AFPS_ERR_WORKSPACE, "workspace must be non-null");
+    hipStream_t stream = (hipStream_t)stream_;
+    unsigned* counters = (unsigned*)workspace;
+    const WorkItem* items = (const WorkItem*)((char*)workspace + kCounterBytes);
+    int nb = (int)plan->buckets.size();
+    void* rargs[] = {&counters, &nb};
+    AFPS_HIP(hipLaunchKernel(queue_reset_kernel(), dim3(1), dim3(64), rargs, 0, stream));
+
+    auto launch_bucket = [&](int b, hipStream_t s) -> int {
+        const Bucket& bk = plan->buckets[b];
+        const WorkItem* first = items + bk.first;
+        int count = bk.count;
+        unsigned* counter = counters + b;
+        void* args[] = {(void*)&xyz_all, (void*)&out_all, (void*)&first, (void*)&count, (void*)&counter};
+        AFPS_HIP(hipLaunchKernel(bk.kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
+        return AFPS_OK;
+    };
+    if (nb == 1) return launch_bucket(0, stream);
+
+    // Several variants: run them concurrently on helper streams (fork / join
+    // through events, which a stream capture records as graph edges).
+    DeviceState* d;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    if ((rc = helper_streams(d))) return rc;
+    AFPS_HIP(hipEventRecord(plan->events[0], stream));
+    const int used = std::min(nb, kHelperStreams);
+    for (int h = 0; h < used; ++h) AFPS_HIP(hipStreamWaitEvent(d->helpers[h], plan->events[0], 0));
+    for (int b = 0; b < nb; ++b)
+        if ((rc = launch_bucket(b, d->helpers[b % kHelperStreams]))) return rc;
+    for (int h = 0; h < used; ++h) {
+        AFPS_HIP(hipEventRecord(plan->events[1 + h], d->helpers[h]));
+        AFPS_HIP(hipStreamWaitEvent(stream, plan->events[1 + h], 0));
+    }
+    return AFPS_OK;
+}
+
+int afps_plan_graph_launch(afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
+                           void* stream_) {
+    if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
+    if (plan->items.empty()) return AFPS_OK;
+    hipStream_t stream = (hipStream_t)stream_;
+    std::lock_guard<std::mutex> lk(plan->mu);
+    if (!plan->exec || plan->g_xyz != xyz_all || plan->g_out != out_all || plan->g_ws != workspace) {
+        if (plan->exec) {
+            (void)hipGraphExecDestroy(plan->exec);
+            plan->exec = nullptr;
+        }
+        // Capture on the plan's own stream (the caller's may be the null
+        // stream, which cannot be captured); replay on the caller's stream.
+        if (!plan->capture) AFPS_HIP(hipStreamCreateWithFlags(&plan->capture, hipStreamNonBlocking));
+        AFPS_HIP(hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal));
+        int rc = afps_plan_launch(plan, xyz_all, out_all, workspace, plan->capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(plan->capture, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        plan->g_xyz = xyz_all;
+        plan->g_out = out_all;
+        plan->g_ws = workspace;
+    }
+    AFPS_HIP(hipGraphLaunch(plan->exec, stream));
+    return AFPS_OK;
+}
+
+size_t afps_batched_workspace_bytes(const afps_cloud_desc* descs, int32_t batch) {
+    afps_plan* p = nullptr;
+    if (afps_plan_create(descs, batch, &p) != AFPS_OK) return 0;
+    const size_t b = p->ws_bytes;
+    afps_plan_destroy(p);
+    return b;
+}
+
+int afps_batched(const float* xyz_all, const afps_cloud_desc* descs, int32_t batch, int32_t* out_all,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+    if (batch > 0 && (!xyz_all || !out_all)) return fail(AFPS_ERR_NULL, "xyz_all and out_all must be non-null");
+    afps_plan* p = nullptr;
+    int rc = afps_plan_create(descs, batch, &p);
+    if (rc) return rc;
+    rc = afps_plan_upload(p, workspace, workspace_bytes, stream);
+    if (!rc) rc = afps_plan_launch(p, xyz_all, out_all, workspace, stream);
+    afps_plan_destroy(p);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Host-visible tables of compiled kernel variants.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace afps {
+
+// One sector's work, as the batch queue hands it out (32 bytes).
+struct WorkItem {
+    int64_t xyz_offset;   // first point of the sector, in points, into xyz_all
+    int64_t out_offset;   // first output of the sector, in indices, into out_all
+    int32_t n;            // points in the sector
+    int32_t c;            // samples of the sector
+    int32_t k;            // NPDU window parameter, < 0 = off
+    int32_t start;        // local start point (start mod n)
+    int32_t base;         // index of the sector's first point inside its cloud
+    int32_t pad;
+};
+
+// Full-update sector kernels (kernels.hip): W waves, P slots per thread.
+struct VariantEntry {
+    int waves;              // W: waves per workgroup (64*W threads)
+    int slots;              // P: point slots per thread; a sector holds <= 64*W*P points
+    int lds_bytes;          // dynamic LDS (distances kept in LDS), 0 = in registers
+    const void* direct;     // direct_kernel<P, W, DL>
+    const void* persistent; // persistent_kernel<P, W, DL>
+};
+
+void register_variants_w1(std::vector<VariantEntry>& v);
+void register_variants_w2(std::vector<VariantEntry>& v);
+void register_variants_w4(std::vector<VariantEntry>& v);
+void register_variants_w8(std::vector<VariantEntry>& v);
+void register_variants_w16(std::vector<VariantEntry>& v);
+
+// NPDU sector kernels (kernels_npdu.hip): one wave, chunks of 64*Q points.
+struct NpduEntry {
+    int chunk64;            // Q: a sector holds <= 64*64*Q points
+    int xyz_in_lds;         // 1: x,y,z and D in LDS (16 B/point); 0: only D (4 B/point)
+    const void* direct;
+    const void* persistent;
+};
+void register_npdu_variants(std::vector<NpduEntry>& v);
+
+// Multi-workgroup plain FPS (fps_grid.hip).
+struct GridVariant {
+    int waves, slots;
+    const void* kernel;
+};
+void register_grid_variants(std::vector<GridVariant>& v);
+const void* grid_reset_kernel();
+const void* queue_reset_kernel();
+constexpr int kMaxGridGroups = 64;     // workgroups meeting at the grid barrier
+constexpr int kGridSyncBytes = 256 + 2 * kMaxGridGroups * 32;   // one barrier block
+
+}  // namespace afps

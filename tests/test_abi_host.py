@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every function include/afps.h declares, and
+rejects bad arguments on the host before touching a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "afps.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2208_08795_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2208_08795_amd import build_lib
+        build_lib.build()
+    return binding.lib()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(afps_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function(L):
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    from paper_2208_08795_amd import binding
+    for st in range(0, -8, -1):
+        assert binding.status_string(st) not in ("", "unknown status")
+    assert binding.status_string(-99) == "unknown status"
+
+
+def test_host_validation_without_gpu(L):
+    from paper_2208_08795_amd import binding
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: validation rejects first
+    assert L.afps_afps(None, 10, 5, 1, 0, dummy, None) == -1
+    assert L.afps_afps(dummy, 10, 5, 1, 0, None, None) == -1
+    assert L.afps_afps(dummy, 10, 11, 1, 0, dummy, None) == -2     # c > n
+    assert L.afps_afps(dummy, 10, 5, 6, 0, dummy, None) == -2      # m > c
+    assert L.afps_afps(dummy, 10, 5, 0, 0, dummy, None) == -2      # m < 1
+    assert L.afps_afps(dummy, 10, 5, 2, 10, dummy, None) == -3     # start >= n
+    assert L.afps_afps(dummy, 10, 5, 2, -1, dummy, None) == -3
+    assert L.afps_afps_npdu(dummy, 10, 5, 2, -1, 0, dummy, None) == -2   # k < 0
+    assert L.afps_fps_plain(dummy, 0, 0, 0, dummy, None) == -2
+    assert "1 <= m <= c <= n" in L.afps_last_error().decode()
+    assert L.afps_set_spin_limit(0) == -2
+    # bad descriptors are rejected before any device work
+    descs, _, _ = binding.descriptors([100, 50], [10, 60], [2, 1], [None, 4], [0, 0])
+    plan = ctypes.c_void_p()
+    assert L.afps_plan_create(ctypes.cast(descs, ctypes.c_void_p), 2, ctypes.byref(plan)) == -2
+    assert "descriptor 1" in L.afps_last_error().decode()
+    assert L.afps_tune_set(100, 0, 3, 5) == -2   # no such variant
+    assert L.afps_max_sector_points() == 32768
+
+
+def test_descriptor_layout():
+    from paper_2208_08795_amd import binding
+    assert ctypes.sizeof(binding.CloudDesc) == 40
+    arr, tp, ts = binding.descriptors([5, 7], [2, 3], [1, 1], [None, 2], [0, 1])
+    assert (arr[1].xyz_offset, arr[1].out_offset, arr[0].k, arr[1].k) == (5, 2, -1, 2)
+    assert (tp, ts) == (12, 5)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2208_08795_amd import binding
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.lib()

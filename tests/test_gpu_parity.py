@@ -1,0 +1,235 @@
+"""GPU parity: every kernel path, index for index against the CPU oracle.
+
+Squared distances use the same fp32 operation order on both sides with
+contraction off, and argmax ties go to the lowest index, so the sampled
+indices must be identical (tolerance 0).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_08795_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2208_08795_amd import binding
+    binding.lib()
+    return binding
+
+
+def _run(B, torch, xyz_t, c, m, k, start, variant=None):
+    if k is None and m == 1 and variant is None:
+        out = B.fps(xyz_t, c, start)
+    elif k is None:
+        out = B.afps(xyz_t, c, m, start, variant=variant)
+    else:
+        out = B.afps_npdu(xyz_t, c, m, k, start, variant=variant)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _check(B, torch, dev, pts, c, m, k, start, variant=None, label=""):
+    print("case %s n=%d c=%d m=%d k=%s start=%d variant=%s" % (label, len(pts), c, m, k, start, variant),
+          flush=True)
+    xyz = torch.from_numpy(np.ascontiguousarray(pts, dtype=np.float32)).to(dev)
+    got = _run(B, torch, xyz, c, m, k, start, variant)
+    want = oracle.afps(pts, c, m, k, start)
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError("%s: %d mismatches, first at %d: got %d want %d" %
+                             (label, bad.size, bad[0], got[bad[0]], want[bad[0]]))
+
+
+def test_hand_examples(B, torch_dev):
+    torch, dev = torch_dev
+    with open(GOLDEN) as f:
+        for case in json.load(f)["cases"]:
+            pts = np.array(case["points"], dtype=np.float32)
+            xyz = torch.from_numpy(pts).to(dev)
+            got = _run(B, torch, xyz, case["c"], case["m"], case["k"], case["start"])
+            assert got.tolist() == case["expected"], case["name"]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "grid", "sorted", "object"])
+def test_random_small_cases(B, torch_dev, kind):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(2024)
+    for it in range(40):
+        n = int(rng.integers(1, 5000))
+        if kind == "uniform":
+            pts = rng.random((n, 3), dtype=np.float32)
+        elif kind == "grid":         # exact ties everywhere
+            pts = rng.integers(0, 4, (n, 3)).astype(np.float32)
+        elif kind == "sorted":
+            pts = synth.uniform_cube(n, int(rng.integers(0, 1 << 30)))
+        else:
+            pts = synth.object_cloud(max(n, 1), int(rng.integers(0, 1 << 30)))
+        c = int(rng.integers(1, min(n, 700) + 1))
+        m = int(rng.integers(1, min(c, 40) + 1))
+        k = [None, None, 0, 1, 7, 32, 64, 129, 4 * n][int(rng.integers(0, 9))]
+        start = int(rng.integers(0, n))
+        _check(B, torch, dev, pts, c, m, k, start, label="%s-%d" % (kind, it))
+
+
+def test_edge_cases(B, torch_dev):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(5)
+    one = rng.random((1, 3), dtype=np.float32)
+    for k in (None, 0, 5):
+        _check(B, torch, dev, one, 1, 1, k, 0, label="single-point")
+    pts = rng.random((300, 3), dtype=np.float32)
+    for c, m, k, start in [(300, 1, None, 299), (300, 300, None, 17), (300, 300, 3, 17), (1, 1, None, 5),
+                           (300, 7, 0, 0), (300, 1, 0, 150), (299, 13, 1 << 30, 2)]:
+        _check(B, torch, dev, pts, c, m, k, start, label="edge")
+    dup = np.repeat(rng.random((40, 3), dtype=np.float32), 5, axis=0)   # duplicate points
+    for k in (None, 3):
+        _check(B, torch, dev, dup, 150, 3, k, 7, label="duplicates")
+
+
+def test_every_full_variant_agrees(B, torch_dev):
+    """All (waves, slots) variants give the oracle's indices (also exercises
+    the cross-wave LDS reduction at every wave count)."""
+    torch, dev = torch_dev
+    for waves in (1, 2, 4, 8, 16):
+        for slots in (1, 2, 4, 8, 12, 16, 24, 32):
+            cap = 64 * waves * slots
+            n = max(2, cap - 37)          # ragged last slot
+            pts = synth.object_cloud(n, seed=waves * 100 + slots)
+            _check(B, torch, dev, pts, min(n, 300), 1, None, n // 3, variant=(waves, slots),
+                   label="variant")
+            if cap >= 128:
+                _check(B, torch, dev, pts, min(n, 300), 3, None, 1, variant=(waves, slots),
+                       label="variant-m3")
+
+
+@pytest.mark.parametrize("q", [1, 2, 4, 8])
+def test_every_npdu_variant_agrees(B, torch_dev, q):
+    torch, dev = torch_dev
+    n = 4096 * q - 101
+    pts = synth.object_cloud(n, seed=q)
+    for k, m, start in [(8, 1, 0), (64, 1, n // 2), (33, 2, 5), (200, 1, 17)]:
+        ns = -(-n // m)
+        if ns > 4096 * q:
+            continue
+        _check(B, torch, dev, pts, min(n // 4, 2000), m, k, start, variant=(1, q), label="npdu-q%d" % q)
+
+
+def test_config1_plain_fps(B, torch_dev):
+    torch, dev = torch_dev
+    pts = synth.uniform_cube(2048, 0)
+    _check(B, torch, dev, pts, 512, 1, None, 0, label="cfg1-fps")
+    _check(B, torch, dev, pts, 512, 1, None, 0, variant=(4, 8), label="cfg1-afps-m1")
+
+
+def test_config2_sweep(B, torch_dev):
+    torch, dev = torch_dev
+    pts = synth.object_cloud(8192, 0)
+    for m in (1, 2, 4, 8, 16, 32):
+        for k in (None, 8, 32, 128):
+            _check(B, torch, dev, pts, 2048, m, k, 0, label="cfg2")
+
+
+def test_config3_lidar(B, torch_dev):
+    torch, dev = torch_dev
+    pts = synth.lidar_scan(512, 0)
+    _check(B, torch, dev, pts, 8192, 16, 64, 0, label="cfg3-npdu")
+    _check(B, torch, dev, pts, 8192, 16, None, 0, label="cfg3-afps")
+    _check(B, torch, dev, pts, 8192, 1, None, 0, label="cfg3-fps")
+
+
+@pytest.mark.parametrize("n,c", [(40000, 600), (131072, 1024), (70001, 3000)])
+def test_grid_fps_large_clouds(B, torch_dev, n, c):
+    torch, dev = torch_dev
+    pts = synth.lidar_scan(-(-n // 64), seed=n, n=n)
+    _check(B, torch, dev, pts, c, 1, None, n // 7, label="grid-fps")
+
+
+def _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=0):
+    sizes = [len(p) for p in clouds]
+    print("batch clouds=%d points=%d ks=%s graph=%d" % (len(clouds), sum(sizes), sorted(set(map(str, ks))),
+                                                      graph_replays), flush=True)
+    plan = B.BatchPlan(sizes, cs, ms, ks, starts, device=dev)
+    xyz_all = torch.from_numpy(np.concatenate(clouds).astype(np.float32)).to(dev)
+    out = plan.launch(xyz_all)
+    torch.cuda.synchronize()
+    eager = out.cpu().numpy().copy()
+    for i, p in enumerate(clouds):
+        o = plan.descs[i].out_offset
+        want = oracle.afps(p, cs[i], ms[i], ks[i], starts[i])
+        assert np.array_equal(eager[o:o + cs[i]], want), "cloud %d" % i
+    for r in range(graph_replays):
+        out.fill_(-7)
+        plan.launch(xyz_all, out_all=out, graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), "graph replay %d" % r
+        torch.zeros(1000, device=dev).sum().item()   # eager work between replays
+    plan.close()
+    return plan
+
+
+def test_batched_uneven_npdu_and_graph(B, torch_dev):
+    torch, dev = torch_dev
+    clouds = synth.batch_of_objects(48, seed=3, n_min=1024, n_max=32768)
+    cs = [len(p) // 4 for p in clouds]
+    _batch_case(B, torch, dev, clouds, cs, [8] * len(clouds), [32] * len(clouds), [0] * len(clouds),
+                graph_replays=3)
+
+
+def test_batched_mixed_variants(B, torch_dev):
+    """Plain FPS, AFPS and NPDU clouds of uneven size in one plan (several
+    persistent launches on helper streams)."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(11)
+    clouds, cs, ms, ks, starts = [], [], [], [], []
+    for i in range(24):
+        n = int(rng.integers(200, 20000))
+        clouds.append(synth.object_cloud(n, seed=int(rng.integers(0, 1 << 30))))
+        kind = i % 3
+        cs.append(max(1, n // 8))
+        ms.append(1 if kind == 0 else int(rng.integers(1, 9)))
+        ks.append(None if kind < 2 else int(rng.integers(0, 80)))
+        starts.append(int(rng.integers(0, n)))
+    _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=2)
+
+
+def test_batched_plain_fps_up_to_32768(B, torch_dev):
+    torch, dev = torch_dev
+    clouds = [synth.object_cloud(n, seed=n) for n in (32768, 30000, 24577, 1024, 5000)]
+    _batch_case(B, torch, dev, clouds, [256] * 5, [1] * 5, [None] * 5, [0, 1, 2, 3, 4])
+
+
+def test_grid_barrier_timeout_is_bounded(B, torch_dev):
+    """A tiny spin limit forces the grid barrier's bounded wait to give up: the
+    kernel must still exit and leave -1 in the outputs it did not finish."""
+    torch, dev = torch_dev
+    pts = synth.lidar_scan(800, seed=1, n=50000)
+    xyz = torch.from_numpy(pts).to(dev)
+    B.set_spin_limit(1)
+    try:
+        out = B.fps(xyz, 400, 0)
+        torch.cuda.synchronize()
+    finally:
+        B.set_spin_limit(1 << 22)
+    got = out.cpu().numpy()
+    want = oracle.fps(pts, 400, 0)
+    # a finished prefix equal to the oracle's, then -1 from the failed iteration on
+    bad = np.flatnonzero(got == -1)
+    f = int(bad[0]) if bad.size else len(got)
+    assert np.array_equal(got[:f], want[:f])
+    assert np.all(got[f:] == -1)
