@@ -1,0 +1,255 @@
+"""Benchmark: batched AFPS-NPDU vs plain FPS on one MI355X.
+
+One step = one pass of the whole sampling path over one batch: 256 object-like
+clouds of uneven size (N log-uniform in [1024, 32768], C = N/4), AFPS with
+M = 8 sectors and NPDU window k = 32, all 2048 sectors in one persistent
+launch (queue reset + persistent kernel, replayed from a hipGraph).  Inputs are
+resident in HBM before the timed region.  The same 256 clouds are also sampled
+with plain FPS (one workgroup per cloud) for comparison.
+
+Prints ONE JSON line (rank 0, N = 1).  Extra fields: plain-FPS figures, per-step
+latency percentiles, single-cloud latencies of the paper-sized configurations,
+coverage radius against plain FPS, the roofline of the dominant kernel and the
+oracle's CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sampled pts/s + p50/p99 frame latency, AFPS-NPDU vs plain FPS, 1 MI355X"
+# MI355X peaks used for the roofline.
+HBM_PEAK_GBS = 8000.0
+# fp32 VALU without FMA and without packed ops (the method's distance is a
+# chain of separately rounded sub/mul/add): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def time_plan(torch, plan, xyz_all, out, steps, warmup, stream):
+    """Warm up, then time exactly `steps` graph launches: wall clock between two
+    synchronisations, plus HIP events around every step on the launch stream."""
+    for _ in range(warmup):
+        plan.launch(xyz_all, out_all=out, graph=True, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        plan.launch(xyz_all, out_all=out, graph=True, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def npdu_work(sizes, cs, out_np, offsets, m, k):
+    """Algorithmic work of AFPS-NPDU, counted from the picks: for every
+    iteration of every sector, 9 fp32 ops per distance update of the window
+    (3 sub, 3 mul, 2 add, 1 min) and one compare per sector point for the
+    argmax the method defines.  Returns (ops, distance updates)."""
+    ops = upd = 0
+    for n, c, o in zip(sizes, cs, offsets):
+        qn, rn, qc, rc = n // m, n % m, c // m, c % m
+        for s in range(m):
+            ns, b = qn + (s < rn), s * qn + min(s, rn)
+            cc, oo = qc + (s < rc), s * qc + min(s, rc)
+            cur = out_np[o + oo:o + oo + cc - 1].astype(np.int64) - b
+            lo = np.maximum(0, cur - k // 2)
+            hi = np.minimum(ns - 1, cur + (k - k // 2))
+            u = int((hi - lo + 1).sum())
+            upd += u
+            ops += 9 * u + (cc - 1) * ns
+    return ops, upd
+
+
+def single_cloud_latency(torch, binding, synth, stream, reps=20):
+    """Single-frame latencies of the paper-sized configurations (ms, median of reps)."""
+    res = {}
+    cases = {
+        "cfg1_fps_n2048_c512": (synth.uniform_cube(2048, 0), dict(kind="fps", c=512)),
+        "cfg3_fps_n32768_c8192": (synth.lidar_scan(512, 0), dict(kind="fps", c=8192)),
+        "cfg3_afps_npdu_m16_k64": (synth.lidar_scan(512, 0), dict(kind="npdu", c=8192, m=16, k=64)),
+        "cfg2_afps_m32_n8192_c2048": (synth.object_cloud(8192, 0), dict(kind="afps", c=2048, m=32)),
+        "cfg2_afps_npdu_m32_k32": (synth.object_cloud(8192, 0), dict(kind="npdu", c=2048, m=32, k=32)),
+        "cfg2_fps_n8192_c2048": (synth.object_cloud(8192, 0), dict(kind="fps", c=2048)),
+    }
+    for name, (pts, p) in cases.items():
+        xyz = torch.from_numpy(pts).cuda()
+        out = torch.empty(p["c"], dtype=torch.int32, device="cuda")
+
+        def run():
+            if p["kind"] == "fps":
+                binding.fps(xyz, p["c"], 0, out=out, stream=stream)
+            elif p["kind"] == "afps":
+                binding.afps(xyz, p["c"], p["m"], 0, out=out, stream=stream)
+            else:
+                binding.afps_npdu(xyz, p["c"], p["m"], p["k"], 0, out=out, stream=stream)
+        for _ in range(2):
+            run()
+        torch.cuda.synchronize()
+        ts = []
+        r = reps if "32768_c8192" not in name else 3
+        for _ in range(r):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            run()
+            b.record(stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        res[name] = round(float(np.median(ts)), 4)
+        log("single %s: %.4f ms" % (name, res[name]))
+    return res
+
+
+def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
+    """The oracle (never tuned) on the host cores: one cloud per task."""
+    import oracle
+    oracle.load()
+    cores = min(16, os.cpu_count() or 1)
+    # bounded sample: clouds in order until the estimated single-core work
+    # (~ N^2 / (8 m) compare steps) reaches the budget
+    est, take = 0.0, 0
+    for p, c in zip(clouds, cs):
+        est += len(p) * c / m * 2e-9
+        take += 1
+        if est > budget_s * cores * 0.5:
+            break
+    idx = list(range(take))
+
+    def one(i):
+        return oracle.afps(clouds[i], cs[i], m, k, 0)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        outs = list(ex.map(one, idx))
+    dt = time.perf_counter() - t0
+    same = all(np.array_equal(outs[j], gpu_out[offsets[i]:offsets[i] + cs[i]]) for j, i in enumerate(idx))
+    samples = sum(cs[i] for i in idx)
+    return {"value": samples / dt, "unit": "sampled pts/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d of the 256 clouds (%d points, %d samples), AFPS M=%d NPDU k=%d, one cloud "
+                      "per thread, %.2f s" % (take, sum(len(clouds[i]) for i in idx), samples, m, k, dt),
+            "matches_gpu": bool(same)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-single", action="store_true", help="skip single-cloud latencies")
+    ap.add_argument("--no-fps", action="store_true", help="skip the plain-FPS comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent clouds would shard by request with no exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_08795_amd import binding, synth
+    from paper_2208_08795_amd.quality import coverage_radius
+
+    binding.lib()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    M, K = 8, 32
+    log("generating 256 clouds")
+    clouds = synth.batch_of_objects(256, seed=args.seed)
+    sizes = [len(p) for p in clouds]
+    cs = [n // 4 for n in sizes]
+    xyz_all = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    total_samples = sum(cs)
+
+    # A plain device copy of known size: rocprofv3 --pmc runs read its
+    # FETCH_SIZE / WRITE_SIZE to calibrate the counters.
+    calib = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    calib2 = torch.empty_like(calib)
+    calib2.copy_(calib)
+
+    plan = binding.BatchPlan(sizes, cs, [M] * 256, [K] * 256, [0] * 256, device=dev)
+    out = torch.empty(plan.total_samples, dtype=torch.int32, device=dev)
+    log("AFPS-NPDU plan: %d items, %d launch(es)" % (plan.items, plan.launches))
+    wall, ev_ms = time_plan(torch, plan, xyz_all, out, args.steps, args.warmup, stream)
+    ms_per_step = wall * 1e3 / args.steps
+    value = total_samples / (wall / args.steps)
+    out_np = out.cpu().numpy()
+    log("AFPS-NPDU: %.3f ms/step, %.3e sampled pts/s" % (ms_per_step, value))
+
+    res = {"metric": METRIC, "value": value, "unit": "sampled pts/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256 object-like clouds, N log-uniform [1024, 32768] (%d points), "
+                                  "C = N/4 (%d samples), AFPS M=8 with NPDU k=32, one persistent launch "
+                                  "per step replayed from a hipGraph" % (sum(sizes), total_samples),
+                      "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples}}
+    res["latency"] = {"unit": "ms", "what": "per step (whole batch of 256 frames), HIP events",
+                      "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
+
+    # Roofline of the dominant kernel (the persistent NPDU kernel is the step).
+    ops, upd = npdu_work(sizes, cs, out_np, plan.offsets, M, K)
+    kern_s = float(np.mean(ev_ms)) / 1e3
+    hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 32 * plan.items
+    res["roofline"] = {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": VALU_PEAK_TOPS,
+                       "unit": "TOPS (fp32 VALU ops)", "frac": ops / kern_s / 1e12 / VALU_PEAK_TOPS,
+                       "traffic": None,
+                       "kernel": "persistent_npdu_kernel<1,true>",
+                       "algorithmic_ops_per_launch": ops, "distance_updates_per_launch": upd,
+                       "hbm_bytes_per_launch": hbm_bytes,
+                       "hbm_frac": hbm_bytes / kern_s / 1e9 / HBM_PEAK_GBS,
+                       "avg_launch_ms": kern_s * 1e3}
+
+    if not args.no_fps:
+        fplan = binding.BatchPlan(sizes, cs, [1] * 256, [None] * 256, [0] * 256, device=dev)
+        fout = torch.empty(fplan.total_samples, dtype=torch.int32, device=dev)
+        fsteps = max(3, args.steps // 4)
+        fwall, fev = time_plan(torch, fplan, xyz_all, fout, fsteps, 1, stream)
+        fvalue = total_samples / (fwall / fsteps)
+        fout_np = fout.cpu().numpy()
+        log("plain FPS: %.3f ms/step, %.3e sampled pts/s" % (fwall * 1e3 / fsteps, fvalue))
+        res["plain_fps"] = {"value": fvalue, "unit": "sampled pts/s", "ms_per_step": fwall * 1e3 / fsteps,
+                            "steps": fsteps, "launches": fplan.launches,
+                            "latency_p50_ms": percentile(fev, 50), "latency_p99_ms": percentile(fev, 99),
+                            "afps_npdu_speedup": value / fvalue}
+        # quality: coverage radius against plain FPS (fp64, 32 clouds)
+        ratios = []
+        for i in range(0, 256, 8):
+            o = plan.offsets[i]
+            r_n = coverage_radius(clouds[i], out_np[o:o + cs[i]])
+            r_f = coverage_radius(clouds[i], fout_np[o:o + cs[i]])
+            ratios.append(r_n / r_f)
+        res["coverage_radius_vs_fps"] = {"mean": float(np.mean(ratios)), "max": float(np.max(ratios)),
+                                         "clouds": len(ratios)}
+        fplan.close()
+
+    if not args.no_single:
+        res["single_cloud_ms"] = single_cloud_latency(torch, binding, synth, stream)
+
+    if not args.no_cpu:
+        log("oracle CPU baseline")
+        res["cpu_baseline"] = cpu_baseline(clouds, cs, M, K, out_np, plan.offsets)
+        log("cpu baseline: %s" % res["cpu_baseline"])
+    plan.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
