@@ -137,7 +137,7 @@ const NpduEntry* choose_npdu(int n) {
     return nullptr;
 }
 
-int npdu_lds_bytes(const NpduEntry& v, int n) { return (v.xyz_in_lds ? 16 : 4) * n; }
+int npdu_lds_bytes(const NpduEntry& v, int n) { return 4 * npdu_lds_words(n, v.xyz_in_lds != 0); }
 
 // ------------------------------------------------------------ devices
 
@@ -464,7 +464,7 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     struct Staged {
         WorkItem item;
         const void* kernel;
-        int block, lds;
+        int block, lds;   // lds: the bucket's dynamic LDS (size class of the sector)
         double cost;
     };
     std::vector<Staged> staged;
@@ -494,7 +494,11 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
                 if (!v) return fail(AFPS_ERR_UNSUPPORTED, where + "NPDU sector too large");
                 st.kernel = v->persistent;
                 st.block = 64;
-                st.lds = npdu_lds_bytes(*v, ns);
+                // LDS size classes (sectors of <= 512, 1024, 2048, 4096... points):
+                // small sectors keep many workgroups resident per CU.
+                int cls = 512;
+                while (cls < ns) cls *= 2;
+                st.lds = npdu_lds_bytes(*v, std::min(cls, capacity(*v)));
                 st.cost = (double)cs * 300.0;   // per-iteration cost roughly independent of n_s
             } else {
                 const VariantEntry* v = ns <= kMaxFullSector ? choose_full(ns) : nullptr;
@@ -511,15 +515,16 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         }
     }
     // Group by kernel; inside a group, longest first.
+    // Group by (kernel, LDS class); inside a group, longest first.
     std::stable_sort(staged.begin(), staged.end(), [](const Staged& a, const Staged& b) {
         if (a.kernel != b.kernel) return a.kernel < b.kernel;
+        if (a.lds != b.lds) return a.lds < b.lds;
         return a.cost > b.cost;
     });
     for (size_t i = 0; i < staged.size();) {
         size_t j = i;
-        Bucket bk{staged[i].kernel, staged[i].block, 0, (int)i, 0, 0, 0.0};
-        while (j < staged.size() && staged[j].kernel == bk.kernel) {
-            bk.lds_bytes = std::max(bk.lds_bytes, staged[j].lds);
+        Bucket bk{staged[i].kernel, staged[i].block, staged[i].lds, (int)i, 0, 0, 0.0};
+        while (j < staged.size() && staged[j].kernel == bk.kernel && staged[j].lds == bk.lds_bytes) {
             bk.cost += staged[j].cost;
             ++j;
         }

@@ -9,7 +9,7 @@
 
 namespace afps {
 
-template <int Q, bool XYZ>
+template <int R, bool XYZ>
 __global__ __launch_bounds__(64) void direct_npdu_kernel(const float* __restrict__ xyz, int n, int c,
                                                          int m, int k, int start,
                                                          int32_t* __restrict__ out) {
@@ -18,10 +18,10 @@ __global__ __launch_bounds__(64) void direct_npdu_kernel(const float* __restrict
     const int qn = n / m, rn = n % m, qc = c / m, rc = c % m;
     const int ns = qn + (s < rn ? 1 : 0), b = s * qn + min(s, rn);
     const int cs = qc + (s < rc ? 1 : 0), o = s * qc + min(s, rc);
-    sample_sector_npdu<Q, XYZ>(xyz + 3 * (int64_t)b, ns, cs, k, start % ns, b, out + o, dyn_lds);
+    sample_sector_npdu<R, XYZ>(xyz + 3 * (int64_t)b, ns, cs, k, start % ns, b, out + o, dyn_lds);
 }
 
-template <int Q, bool XYZ>
+template <int R, bool XYZ>
 __global__ __launch_bounds__(64) void persistent_npdu_kernel(const float* __restrict__ xyz_all,
                                                              int32_t* __restrict__ out_all,
                                                              const WorkItem* __restrict__ items,
@@ -33,16 +33,16 @@ __global__ __launch_bounds__(64) void persistent_npdu_kernel(const float* __rest
         const unsigned it = (unsigned)__builtin_amdgcn_readfirstlane((int)v);
         if (it >= (unsigned)n_items) break;   // every workgroup ends once the queue is drained
         const WorkItem wi = items[it];
-        sample_sector_npdu<Q, XYZ>(xyz_all + 3 * wi.xyz_offset, wi.n, wi.c, wi.k, wi.start, wi.base,
+        sample_sector_npdu<R, XYZ>(xyz_all + 3 * wi.xyz_offset, wi.n, wi.c, wi.k, wi.start, wi.base,
                                    out_all + wi.out_offset, dyn_lds);
         __syncthreads();   // LDS of this item is dead before the next item's load
     }
 }
 
-template <int Q, bool XYZ>
+template <int R, bool XYZ>
 static void add(std::vector<NpduEntry>& v) {
-    v.push_back({Q, XYZ ? 1 : 0, (const void*)&direct_npdu_kernel<Q, XYZ>,
-                 (const void*)&persistent_npdu_kernel<Q, XYZ>});
+    v.push_back({R, XYZ ? 1 : 0, (const void*)&direct_npdu_kernel<R, XYZ>,
+                 (const void*)&persistent_npdu_kernel<R, XYZ>});
 }
 
 void register_npdu_variants(std::vector<NpduEntry>& v) {

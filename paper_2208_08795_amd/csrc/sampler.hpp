@@ -14,13 +14,9 @@
 //   LDS (double-buffered by iteration parity: one barrier per iteration).
 //
 // sample_sector_npdu (Sec. III-C: update only the window around the sample)
-//   One wave, sector in LDS (x, y, z and D), cut into at most 64 chunks of
-//   64*Q consecutive points; lane q keeps chunk q's maximum and the lowest
-//   index reaching it.  Per iteration the wave updates the window (one lane
-//   per point), re-reduces only the chunks whose recorded maximum lay inside
-//   the window (distances only decrease, so no other chunk maximum can
-//   change), and takes the max over the 64 chunk lanes; chunk order is index
-//   order, so the lowest lane at the max holds the lowest index.
+//   One wave, sector in LDS (x, y, z and D), cut into blocks of 64 points
+//   whose maxima live one per lane; per iteration one LDS round trip, the
+//   window update, and a re-reduction of the one or two window blocks only.
 //
 // Distances are kept as fp32 bit patterns: every distance is >= +0, so
 // unsigned order equals float order and min / max are exact integer ops.
@@ -75,18 +71,31 @@ __device__ __forceinline__ uint32_t row_min(uint32_t v) {
     v = min(v, dpp<0x140>(v));
     return v;
 }
-// Whole-wave max, returned wave-uniform.
+// DPP with a row mask: rows outside `ROWS` receive 0 (the identity of an
+// unsigned max), rows inside receive the permuted value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_rows(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+// Whole-wave max, returned wave-uniform: row maxima, then row_bcast:15 folds
+// row 0 into row 1 and row 2 into row 3, row_bcast:31 folds lane 31 into rows
+// 2 and 3; lane 63 ends with the maximum of all 64 lanes.
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     v = row_max(v);
-    uint32_t a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
-    return max(max(a, b), max(c, d));
+    v = max(v, dpp_rows<0x142, 0xA>(v));   // row_bcast:15 into rows 1, 3
+    v = max(v, dpp_rows<0x143, 0xC>(v));   // row_bcast:31 into rows 2, 3
+    return readlane(v, 63);
 }
-// Whole-wave min, returned wave-uniform.
+// Whole-wave min, returned wave-uniform (rows outside the mask see UINT_MAX).
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
     v = row_min(v);
-    uint32_t a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
-    return min(min(a, b), min(c, d));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xA, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x143, 0xC, 0xF, false));
+    return readlane(v, 63);
 }
+// Lanes where pred holds, as a wave-uniform 64-bit mask.
+__device__ __forceinline__ uint64_t ballot(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 
 __device__ __forceinline__ uint32_t sq_dist_bits(float x, float y, float z,
                                                  float px, float py, float pz) {
@@ -168,18 +177,24 @@ __device__ __forceinline__ Pick update_and_pick(int ns, int w, int lane,
                                                 float px, float py, float pz) {
     uint32_t m = 0u;
     int sl = 0;
+    // Slots are guarded in groups of four (one scalar branch per group);
+    // slots past the sector inside a live group hold D = 0 and stay 0.
+    constexpr int G = P < 4 ? P : 4;
 #pragma unroll
-    for (int s = 0; s < P; ++s) {
-        if (s < ns) {
-            const uint32_t d = min(D.get(s), sq_dist_bits(X[s], Y[s], Z[s], px, py, pz));
-            D.set(s, d);
-            // lane-local maximum, lowest slot on ties (ascending, strict >)
-            if (s == 0 || d > m) { m = d; sl = s; }
+    for (int g = 0; g < P; g += G) {
+        if (g == 0 || g < ns) {
+#pragma unroll
+            for (int s = g; s < g + G; ++s) {
+                const uint32_t d = min(D.get(s), sq_dist_bits(X[s], Y[s], Z[s], px, py, pz));
+                D.set(s, d);
+                // lane-local maximum, lowest slot on ties (ascending, strict >)
+                if (s == 0 || d > m) { m = d; sl = s; }
+            }
         }
     }
     Pick p;
     p.d = wave_max(m);
-    const uint64_t at_max = __ballot(m == p.d);
+    const uint64_t at_max = ballot(m == p.d);
     int l = (int)__builtin_ctzll(at_max);
     int sw = (int)readlane((uint32_t)sl, l);
     if (at_max & (at_max - 1)) {
@@ -220,12 +235,12 @@ __device__ __forceinline__ Pick combine_waves(Pick mine, Candidate* lds, int par
             lx = buf[lane].x; ly = buf[lane].y; lz = buf[lane].z;
         }
         const uint32_t g = readlane(row_max(ld), 0);
-        const uint64_t tie = __ballot(lane < W && ld == g);
+        const uint64_t tie = ballot(lane < W && ld == g);
         int win = (int)__builtin_ctzll(tie);
         if (tie & (tie - 1)) {
             const uint32_t key = ((tie >> lane) & 1) ? li : 0xFFFFFFFFu;
             const uint32_t lowest = readlane(row_min(key), 0);
-            win = (int)__builtin_ctzll(__ballot(key == lowest));
+            win = (int)__builtin_ctzll(ballot(key == lowest));
         }
         Pick p;
         p.d = g;
@@ -270,103 +285,158 @@ __device__ __forceinline__ void sample_sector(const float* __restrict__ xyz, int
     }
 }
 
-// Replace lane `lane` of `old` by the wave-uniform `v`.
-__device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t v, int lane) {
-    return (int)(threadIdx.x & 63) == lane ? v : old;
-}
-
 // NPDU on one sector (Sec. III-C), one wave.
 //   xyz   : the sector's first point in global memory
-//   n, c  : points and samples (1 <= c <= n <= 64*64*Q)
+//   n, c  : points and samples (1 <= c <= n <= 4096*R)
 //   k     : window parameter, 0 <= k <= 2n; the window of sample `cur` is
 //           [cur - floor(k/2), cur + ceil(k/2)] cut to [0, n-1]
 //   cur   : local start point
-//   lds   : (XYZ_IN_LDS ? 4n : n) words of shared memory: x,y,z (row-major),
-//           then D
-// XYZ_IN_LDS = false reads window coordinates from global memory (L2) and
+//   lds   : npdu_lds_words(n, XYZ_IN_LDS) words of shared memory
+// The sector is cut into blocks of 64 consecutive points; lane l of block
+// register r describes block 64r + l: its maximum distance (bm) and the lowest
+// index reaching it (bi).  Distances only decrease and only inside the
+// window, so every block outside the window keeps its (bm, bi).  Per
+// iteration: one LDS round trip brings the new sample's coordinates and the
+// two blocks holding the window (x, y, z, D); while it is in flight the wave
+// reduces the out-of-window blocks; then it updates the window points,
+// re-reduces the two blocks from registers and takes the maximum, ties to the
+// lowest index.  LDS holds x, y, z and D as separate arrays padded with one
+// empty block (D = 0, never a window point), so block reads need no bounds
+// test.  XYZ_IN_LDS = false reads coordinates from global memory (L2) and
 // keeps only D in LDS, for sectors too large for 16 bytes per point.
-template <int Q, bool XYZ_IN_LDS>
+template <int R, bool XYZ_IN_LDS>
 __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz, int n, int c,
                                                    int k, int cur, int base,
                                                    int32_t* __restrict__ out, uint32_t* lds) {
-    constexpr int CH = 64 * Q;   // points per chunk
     const int lane = threadIdx.x & 63;
-    float* sxyz = reinterpret_cast<float*>(lds);
-    uint32_t* sd = lds + (XYZ_IN_LDS ? 3 * n : 0);
+    const int nb = (n + 63) >> 6;                 // blocks holding points
+    const int np = npdu_padded_points(n);
+    float* sx = reinterpret_cast<float*>(lds);
+    float* sy = sx + np;
+    float* sz = sy + np;
+    uint32_t* sd = lds + (XYZ_IN_LDS ? 3 * np : 0);
 
     if constexpr (XYZ_IN_LDS) {
-        const int words = 3 * n;
-        int e = lane;
-        for (; e + 192 < words; e += 256) {
-            const float a = xyz[e], b = xyz[e + 64], cc = xyz[e + 128], d = xyz[e + 192];
-            sxyz[e] = a; sxyz[e + 64] = b; sxyz[e + 128] = cc; sxyz[e + 192] = d;
+        int j = lane;
+        for (; j + 192 < np; j += 256) {          // four points in flight per lane
+            float v[12];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jj = j + 64 * u;
+                const bool ok = jj < n;
+                v[3 * u] = ok ? xyz[3 * jj] : 0.f;
+                v[3 * u + 1] = ok ? xyz[3 * jj + 1] : 0.f;
+                v[3 * u + 2] = ok ? xyz[3 * jj + 2] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sx[j + 64 * u] = v[3 * u]; sy[j + 64 * u] = v[3 * u + 1]; sz[j + 64 * u] = v[3 * u + 2];
+            }
         }
-        for (; e < words; e += 64) sxyz[e] = xyz[e];
+        for (; j < np; j += 64) {
+            const bool ok = j < n;
+            sx[j] = ok ? xyz[3 * j] : 0.f;
+            sy[j] = ok ? xyz[3 * j + 1] : 0.f;
+            sz[j] = ok ? xyz[3 * j + 2] : 0.f;
+        }
     }
-    for (int j = lane; j < n; j += 64) sd[j] = __float_as_uint(kInitialDistance);
+    for (int j = lane; j < np; j += 64) sd[j] = j < n ? __float_as_uint(kInitialDistance) : 0u;
     __syncthreads();
 
-    // Chunk q = points [q*CH, q*CH + CH): lane q holds its maximum and the
-    // lowest index reaching it.  Initially every distance is 1e10.
-    const int nq = (n + CH - 1) / CH;
-    uint32_t cm = lane < nq ? __float_as_uint(kInitialDistance) : 0u;
-    uint32_t ci = lane < nq ? (uint32_t)(lane * CH) : 0xFFFFFFFFu;
-
-    auto point = [&](int j, float& x, float& y, float& z) {
-        if constexpr (XYZ_IN_LDS) { x = sxyz[3 * j]; y = sxyz[3 * j + 1]; z = sxyz[3 * j + 2]; }
-        else { x = xyz[3 * j]; y = xyz[3 * j + 1]; z = xyz[3 * j + 2]; }
-    };
-    float px, py, pz;
-    point(cur, px, py, pz);
+    uint32_t bm[R], bi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int blk = 64 * r + lane;
+        bm[r] = blk < nb ? __float_as_uint(kInitialDistance) : 0u;
+        bi[r] = blk < nb ? (uint32_t)(64 * blk) : 0xFFFFFFFFu;
+    }
+    const int below = k >> 1, above = k - (k >> 1);
     if (lane == 0) out[0] = base + cur;
 
     for (int i = 1; i < c; ++i) {
-        const int lo = max(0, cur - (k >> 1));
-        const int hi = min(n - 1, cur + (k - (k >> 1)));
-        // Window update: one lane per point.
-        for (int j0 = lo; j0 <= hi; j0 += 64) {
-            const int j = j0 + lane;
-            if (j <= hi) {
-                float x, y, z;
-                point(j, x, y, z);
-                sd[j] = min(sd[j], sq_dist_bits(x, y, z, px, py, pz));
-            }
+        const int lo = max(0, cur - below);
+        const int hi = min(n - 1, cur + above);
+        const int blo = lo >> 6, bhi = hi >> 6;
+        const uint32_t span = (uint32_t)(hi - lo);
+
+        // Loads: the sample's coordinates and the first two window blocks.
+        const int j0 = 64 * blo + lane, j1 = j0 + 64;
+        uint32_t d0 = sd[j0], d1 = sd[j1];
+        float px, py, pz, x0, y0, z0, x1, y1, z1;
+        if constexpr (XYZ_IN_LDS) {
+            px = sx[cur]; py = sy[cur]; pz = sz[cur];
+            x0 = sx[j0]; y0 = sy[j0]; z0 = sz[j0];
+            x1 = sx[j1]; y1 = sy[j1]; z1 = sz[j1];
+        } else {
+            px = xyz[3 * cur]; py = xyz[3 * cur + 1]; pz = xyz[3 * cur + 2];
+            const bool ok0 = j0 < n, ok1 = j1 < n;
+            x0 = ok0 ? xyz[3 * j0] : 0.f; y0 = ok0 ? xyz[3 * j0 + 1] : 0.f; z0 = ok0 ? xyz[3 * j0 + 2] : 0.f;
+            x1 = ok1 ? xyz[3 * j1] : 0.f; y1 = ok1 ? xyz[3 * j1 + 1] : 0.f; z1 = ok1 ? xyz[3 * j1 + 2] : 0.f;
         }
-        // Re-reduce the chunks whose recorded maximum the window lowered.
-        for (int q = lo / CH; q <= hi / CH; ++q) {
-            const int at = (int)readlane(ci, q);
-            if (at < lo || at > hi) continue;
-            uint32_t m = 0;
-            int rb = 0;
-            bool valid = false;
+
+        // Best block outside the window's blocks [blo, bhi]: maximum, then the
+        // lowest index.  Independent of the loads above: overlaps them.
+        uint32_t mo = 0u;
 #pragma unroll
-            for (int r = 0; r < Q; ++r) {
-                const int j = q * CH + 64 * r + lane;
-                if (j < n) {
-                    const uint32_t v = sd[j];
-                    if (!valid || v > m) { m = v; rb = r; valid = true; }
-                }
-            }
-            const uint32_t g = wave_max(m);
-            const uint64_t top = __ballot(valid && m == g);
-            uint32_t best;
-            if (Q == 1 || !(top & (top - 1))) {
-                const int l = (int)__builtin_ctzll(top);
-                best = (uint32_t)(q * CH + 64 * (int)readlane((uint32_t)rb, l) + l);
-            } else {
-                const uint32_t key = (valid && m == g) ? (uint32_t)(64 * rb + lane) : 0xFFFFFFFFu;
-                best = (uint32_t)(q * CH) + wave_min(key);
-            }
-            cm = writelane(cm, g, q);
-            ci = writelane(ci, best, q);
+        for (int r = 0; r < R; ++r) {
+            const uint32_t rel = (uint32_t)(64 * r + lane - blo);
+            mo = max(mo, rel > (uint32_t)(bhi - blo) ? bm[r] : 0u);
         }
-        // Max over chunks; chunk order is index order, so the lowest lane at
-        // the maximum holds the lowest index.  Lanes past the last chunk hold
-        // 0 and lie above every real chunk.
-        const uint32_t g = wave_max(cm);
-        const int qw = (int)__builtin_ctzll(__ballot(cm == g));
-        cur = (int)readlane(ci, qw);
-        point(cur, px, py, pz);
+        uint32_t g_best = wave_max(mo);
+        uint32_t i_best = 0xFFFFFFFFu;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t rel = (uint32_t)(64 * r + lane - blo);
+            const uint64_t hit = ballot(rel > (uint32_t)(bhi - blo) && bm[r] == g_best);
+            if (i_best == 0xFFFFFFFFu && hit) i_best = readlane(bi[r], (int)__builtin_ctzll(hit));
+        }
+
+        // Window update of the two blocks (points outside the window keep D).
+        {
+            const uint32_t e0 = min(d0, sq_dist_bits(x0, y0, z0, px, py, pz));
+            const uint32_t e1 = min(d1, sq_dist_bits(x1, y1, z1, px, py, pz));
+            d0 = (uint32_t)(j0 - lo) <= span ? e0 : d0;
+            d1 = (uint32_t)(j1 - lo) <= span ? e1 : d1;
+            sd[j0] = d0;
+            sd[j1] = d1;
+        }
+        // Re-reduce both blocks (independent chains interleave); the second
+        // may be the empty padding block, whose candidates lie past n and
+        // never win against a real point.
+        const uint32_t g0 = wave_max(d0), g1 = wave_max(d1);
+        const uint32_t i0 = (uint32_t)(64 * blo) + (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+        const uint32_t i1 = (uint32_t)(64 * blo + 64) + (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int blk = 64 * r + lane;
+            bm[r] = blk == blo ? g0 : (blk == blo + 1 && blk < nb ? g1 : bm[r]);
+            bi[r] = blk == blo ? i0 : (blk == blo + 1 && blk < nb ? i1 : bi[r]);
+        }
+        if (g0 > g_best || (g0 == g_best && i0 < i_best)) { g_best = g0; i_best = i0; }
+        if (g1 > g_best || (g1 == g_best && i1 < i_best)) { g_best = g1; i_best = i1; }
+
+        // Windows wider than two blocks (k > 64): the remaining blocks.
+        for (int b = blo + 2; b <= bhi; ++b) {
+            const int j = 64 * b + lane;
+            uint32_t d = sd[j];
+            if ((uint32_t)(j - lo) <= span) {
+                float x, y, z;
+                if constexpr (XYZ_IN_LDS) { x = sx[j]; y = sy[j]; z = sz[j]; }
+                else { x = xyz[3 * j]; y = xyz[3 * j + 1]; z = xyz[3 * j + 2]; }
+                d = min(d, sq_dist_bits(x, y, z, px, py, pz));
+                sd[j] = d;
+            }
+            const uint32_t g = wave_max(d);
+            const uint32_t idx = (uint32_t)(64 * b) + (uint32_t)__builtin_ctzll(ballot(d == g));
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int blk = 64 * r + lane;
+                bm[r] = blk == b ? g : bm[r];
+                bi[r] = blk == b ? idx : bi[r];
+            }
+            if (g > g_best || (g == g_best && idx < i_best)) { g_best = g; i_best = idx; }
+        }
+        cur = (int)i_best;
         if (lane == 0) out[i] = base + cur;
     }
 }

@@ -1,6 +1,7 @@
 // Host-visible tables of compiled kernel variants.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <vector>
@@ -34,14 +35,22 @@ void register_variants_w4(std::vector<VariantEntry>& v);
 void register_variants_w8(std::vector<VariantEntry>& v);
 void register_variants_w16(std::vector<VariantEntry>& v);
 
-// NPDU sector kernels (kernels_npdu.hip): one wave, chunks of 64*Q points.
+// NPDU sector kernels (kernels_npdu.hip): one wave, blocks of 64 points whose
+// maxima live in R registers (one block per lane).
 struct NpduEntry {
-    int chunk64;            // Q: a sector holds <= 64*64*Q points
+    int chunk64;            // R: a sector holds <= 64*64*R points
     int xyz_in_lds;         // 1: x,y,z and D in LDS (16 B/point); 0: only D (4 B/point)
     const void* direct;
     const void* persistent;
 };
 void register_npdu_variants(std::vector<NpduEntry>& v);
+
+// LDS of an NPDU sector of n points: x, y, z (if held in LDS) and D arrays,
+// each padded with one empty block of 64 points.
+__host__ __device__ constexpr int npdu_padded_points(int n) { return ((n + 63) / 64 + 1) * 64; }
+__host__ __device__ constexpr int npdu_lds_words(int n, bool xyz_in_lds) {
+    return (xyz_in_lds ? 4 : 1) * npdu_padded_points(n);
+}
 
 // Multi-workgroup plain FPS (fps_grid.hip).
 struct GridVariant {
