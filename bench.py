@@ -120,6 +120,47 @@ def single_cloud_latency(torch, binding, synth, stream, reps=20):
     return res
 
 
+def serving(torch, rates=(50, 200, 800), frames_npdu=160, frames_fps=24, pool=48, seed=1):
+    """Open-loop Poisson streams of LiDAR frames (N uniform in [16384, 131072],
+    C = N/8, M in {8, 16, 32}, k = 64) through the continuous-batching server,
+    AFPS-NPDU and plain FPS, per-frame latency from arrival to completion."""
+    from paper_2208_08795_amd import synth
+    from paper_2208_08795_amd.serve import GpuExecutor, Request, Scheduler, latency_summary
+    rng = np.random.default_rng(seed)
+    log("generating %d serving frames" % pool)
+    frames = synth.frame_stream(rate=1.0, count=pool, seed=seed)
+    pinned = [torch.from_numpy(f.points).pin_memory() for f in frames]
+    budget = 256 << 20
+    ex = GpuExecutor(budget, streams=4)
+    res = {"budget_bytes": budget, "frames": "pool of %d distinct synthetic 64-beam frames, N uniform "
+                                                "in [16384, 131072], C = N/8, M in {8,16,32}, k = 64" % pool}
+
+    def stream(method, count, lam):
+        gaps = rng.exponential(1.0 / lam, count)
+        arr = np.cumsum(gaps) - gaps[0]
+        reqs = []
+        for i in range(count):
+            f = frames[i % pool]
+            m, k = (f.m, f.k) if method == "afps_npdu" else (1, None)
+            reqs.append(Request(i, f.points.shape[0], f.c, m, k, 0, float(arr[i]), pinned[i % pool]))
+        s = Scheduler(ex, budget, max_inflight=8, max_batch=32)
+        done = s.run(reqs)
+        torch.cuda.synchronize()
+        out = latency_summary(done)
+        out.update({"offered_fps": lam, "peak_waiting": s.peak_waiting, "peak_arena_bytes": s.peak_bytes})
+        return out
+
+    for method, count in (("afps_npdu", frames_npdu), ("plain_fps", frames_fps)):
+        stream(method, 6, 1000.0)            # warm-up (plans, kernel attributes)
+        res[method] = {}
+        for lam in rates:
+            r = stream(method, count, float(lam))
+            res[method][str(lam)] = r
+            log("serve %s @%d/s: p50 %.2f ms p99 %.2f ms, %.3e pts/s, peak queue %d" %
+                (method, lam, r["p50_ms"], r["p99_ms"], r["sampled_pts_per_s"] or 0, r["peak_waiting"]))
+    return res
+
+
 def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
     """The oracle (never tuned) on the host cores: one cloud per task."""
     import oracle
@@ -158,6 +199,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-single", action="store_true", help="skip single-cloud latencies")
     ap.add_argument("--no-fps", action="store_true", help="skip the plain-FPS comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving streams")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -201,8 +243,8 @@ def main():
                                   "C = N/4 (%d samples), AFPS M=8 with NPDU k=32, one persistent launch "
                                   "per step replayed from a hipGraph" % (sum(sizes), total_samples),
                       "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples}}
-    res["latency"] = {"unit": "ms", "what": "per step (whole batch of 256 frames), HIP events",
-                      "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
+    res["batch_latency"] = {"unit": "ms", "what": "per step (whole batch of 256 clouds), HIP events",
+                            "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
 
     # Roofline of the dominant kernel (the persistent NPDU kernel is the step).
     ops, upd = npdu_work(sizes, cs, out_np, plan.offsets, M, K)
@@ -242,6 +284,12 @@ def main():
 
     if not args.no_single:
         res["single_cloud_ms"] = single_cloud_latency(torch, binding, synth, stream)
+
+    if not args.no_serve:
+        res["serving"] = serving(torch)
+        mid = res["serving"]["afps_npdu"]["200"]
+        res["latency"] = {"unit": "ms", "what": "per frame, arrival to completion, AFPS-NPDU serving "
+                                               "at 200 frames/s", "p50": mid["p50_ms"], "p99": mid["p99_ms"]}
 
     if not args.no_cpu:
         log("oracle CPU baseline")

@@ -1,0 +1,104 @@
+"""Serving scheduler on the CPU: a fake executor and a fake clock check
+admission by footprint, FIFO order, slot reuse, rejection and launch failure."""
+import random
+
+from paper_2208_08795_amd.serve import ALIGN, Arena, Request, Scheduler, footprint
+
+
+class FakeClock:
+    def __init__(self, dt=1e-4):
+        self.t, self.dt = 0.0, dt
+
+    def __call__(self):
+        self.t += self.dt
+        return self.t
+
+
+class FakeExecutor:
+    """A batch takes 1 ms per frame; launches of frames in fail_ids raise."""
+
+    def __init__(self, clock, fail_ids=()):
+        self.clock, self.fail_ids = clock, set(fail_ids)
+        self.launched = []
+        self.live_bytes = []
+
+    def launch(self, batch):
+        if any(r.rid in self.fail_ids for r in batch.requests):
+            raise RuntimeError("forced launch failure")
+        self.launched.append([r.rid for r in batch.requests])
+        return self.clock.t + 1e-3 * len(batch.requests)
+
+    def done(self, handle):
+        return self.clock.t >= handle
+
+    def finish(self, batch):
+        pass
+
+
+def _req(i, n, arrival, m=8, k=64):
+    return Request(rid=i, n=n, c=n // 8, m=m, k=k, start=0, arrival=arrival)
+
+
+def test_arena_first_fit_and_coalescing():
+    a = Arena(10 * ALIGN)
+    x = a.alloc(1)
+    y = a.alloc(2 * ALIGN)
+    z = a.alloc(ALIGN + 1)
+    assert (x, y, z) == (0, ALIGN, 3 * ALIGN)
+    assert a.alloc(6 * ALIGN) is None and a.alloc(5 * ALIGN) == 5 * ALIGN
+    a.free(y)
+    a.free(x)
+    assert a.free_list[0] == (0, 3 * ALIGN)        # coalesced
+    a.free(z)
+    assert a.free_list[0] == (0, 5 * ALIGN)
+    assert all(off % 12 == 0 and off % 256 == 0 for off in (x, y, z))
+
+
+def test_admission_never_exceeds_budget_and_all_finish():
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    budget = 3 * 1024 * 1024
+    s = Scheduler(ex, budget, max_inflight=3, max_batch=4, clock=clock)
+    rng = random.Random(0)
+    reqs = [_req(i, rng.randint(16384, 131072), 0.0005 * i) for i in range(60)]
+    done = s.run(reqs)
+    assert len(done) == 60 and all(r.state == "done" for r in done)
+    assert s.peak_bytes <= s.arena.size
+    assert s.arena.bytes_used == 0 and s.arena.free_list == [(0, s.arena.size)]
+    # FIFO: admission order equals arrival order
+    order = [rid for b in ex.launched for rid in b]
+    assert order == sorted(order)
+    # continuous batching: some batch held more than one frame, and work overlapped
+    assert max(len(b) for b in ex.launched) > 1
+    assert all(r.latency > 0 for r in done)
+
+
+def test_oversized_frame_is_rejected_and_loop_continues():
+    clock = FakeClock()
+    s = Scheduler(FakeExecutor(clock), 1 << 20, clock=clock)
+    reqs = [_req(0, 20000, 0.0), _req(1, 200000, 0.0), _req(2, 30000, 0.001)]
+    done = {r.rid: r for r in s.run(reqs)}
+    assert done[1].state == "rejected" and "budget" in done[1].error
+    assert done[0].state == "done" and done[2].state == "done"
+
+
+def test_launch_failure_frees_memory_and_others_complete():
+    clock = FakeClock()
+    s = Scheduler(FakeExecutor(clock, fail_ids={3}), 8 << 20, max_batch=1, clock=clock)
+    reqs = [_req(i, 50000, 0.0002 * i) for i in range(8)]
+    done = {r.rid: r for r in s.run(reqs)}
+    assert done[3].state == "failed" and "forced" in done[3].error
+    assert all(done[i].state == "done" for i in range(8) if i != 3)
+    assert s.arena.bytes_used == 0
+
+
+def test_slots_are_reused_under_a_small_budget():
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    one = sum(-(-x // ALIGN) * ALIGN for x in footprint(_req(0, 60000, 0))[:2]) + 2 * ALIGN
+    s = Scheduler(ex, one + ALIGN, max_inflight=4, clock=clock)   # room for one frame at a time
+    reqs = [_req(i, 60000, 0.0) for i in range(5)]
+    done = s.run(reqs)
+    assert all(r.state == "done" for r in done)
+    assert all(len(b) == 1 for b in ex.launched) and len(ex.launched) == 5
+    assert s.peak_waiting >= 4
