@@ -200,6 +200,7 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip single-cloud latencies")
     ap.add_argument("--no-fps", action="store_true", help="skip the plain-FPS comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving streams")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (built-in variant rule)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -258,6 +259,14 @@ def main():
                        "hbm_bytes_per_launch": hbm_bytes,
                        "hbm_frac": hbm_bytes / kern_s / 1e9 / HBM_PEAK_GBS,
                        "avg_launch_ms": kern_s * 1e3}
+
+    if not args.no_tune:
+        from paper_2208_08795_amd import autotune
+        log("autotuning full-update variants")
+        tab = autotune.tune(log=log)
+        res["autotune"] = {k: [[int(n), int(w), int(p), round(ms, 4)] for n, w, p, ms in v]
+                           for k, v in tab.items() if k != "seconds"}
+        res["autotune"]["seconds"] = round(tab["seconds"], 2)
 
     if not args.no_fps:
         fplan = binding.BatchPlan(sizes, cs, [1] * 256, [None] * 256, [0] * 256, device=dev)

@@ -157,12 +157,19 @@ int afps_batched(const float *xyz_all, const afps_cloud_desc *descs, int32_t bat
 /* ------------------------------------------------------------- tuning */
 
 /*
- * Kernel variant chosen for a sector of n_s points (k < 0: no NPDU):
- * waves per workgroup and point slots per thread.  Tuned entries override the
- * built-in rule; afps_tune_set is what the autotuner calls.
+ * Kernel variant chosen for a sector of n_s points: waves per workgroup and
+ * point slots per thread.  `kind` selects the table: AFPS_TUNE_DIRECT (FPS /
+ * AFPS single-cloud launches), AFPS_TUNE_BATCH (FPS / AFPS sectors inside batch
+ * plans), AFPS_TUNE_NPDU (reports the NPDU variant: one wave, `slots` = block
+ * registers).  Tuned entries ("for sectors of at most n_s_max points use this
+ * variant") override the built-in rule; afps_tune_set is what the autotuner
+ * calls, and a file named by the environment variable AFPS_TUNE_CACHE (lines
+ * "direct|batch n_s_max waves slots") is read once at first use.
+ * afps_tune_set returns AFPS_ERR_ARG for an unknown or too small variant.
  */
-int afps_tune_get(int32_t n_s, int32_t k, int32_t *waves, int32_t *slots);
-int afps_tune_set(int32_t n_s_max, int32_t npdu, int32_t waves, int32_t slots);
+enum { AFPS_TUNE_DIRECT = 0, AFPS_TUNE_NPDU = 1, AFPS_TUNE_BATCH = 2 };
+int afps_tune_get(int32_t n_s, int32_t kind, int32_t *waves, int32_t *slots);
+int afps_tune_set(int32_t n_s_max, int32_t kind, int32_t waves, int32_t slots);
 void afps_tune_reset(void);
 
 /*

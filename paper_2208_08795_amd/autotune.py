@@ -1,0 +1,97 @@
+"""Autotuner for the full-update (FPS / AFPS) sector kernels.
+
+For every sector-size class it times each compiled (waves per workgroup,
+point slots per thread) variant that holds the class, on a synthetic object
+cloud, in two regimes, and installs the fastest through the library's tuning
+table:
+
+* ``direct`` (latency): one sector alone on the GPU, the single-cloud calls;
+  time per iteration is set by the per-iteration reduction chain, so fewer
+  waves can win even though they do more work per thread;
+* ``batch`` (throughput): many sectors of the class in one launch, as inside
+  a batch plan; here the variant that keeps the SIMDs busiest wins.
+
+The NPDU kernels are not tuned: they run one wave per sector by design and
+their variant follows from the sector size.  Results can be written to a
+cache file that the library reads at first use (AFPS_TUNE_CACHE).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+WAVES = (1, 2, 4, 8, 16)
+SLOTS = (1, 2, 4, 8, 12, 16, 24, 32)
+CLASSES = (64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 24576, 32768)
+
+
+def candidates(n: int, oversize: int = 4):
+    """Variants holding n points without more than `oversize` times the slots needed."""
+    out = []
+    for w in WAVES:
+        for p in SLOTS:
+            cap = 64 * w * p
+            if cap >= n and cap < oversize * n + 64 * w:
+                out.append((w, p))
+    return out
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def tune(classes=CLASSES, reps: int = 3, batch_points: int = 1 << 22, max_iters: int = 512,
+         install: bool = True, cache_path: str | None = None, seed: int = 0, log=None):
+    """Time the candidates of every class; return {"direct": [...], "batch": [...]}
+    rows of (n_max, waves, slots, ms) and install them in the library."""
+    import torch
+
+    from . import binding, synth
+    t0 = time.perf_counter()
+    table = {"direct": [], "batch": []}
+    for n in classes:
+        c = max(1, min(n // 4, max_iters))
+        single = torch.from_numpy(synth.object_cloud(n, seed)).cuda()
+        sectors = int(np.clip(batch_points // n, 256, 4096))
+        many = torch.from_numpy(np.tile(synth.object_cloud(n, seed + 1), (sectors, 1))).cuda()
+        out1 = torch.empty(c, dtype=torch.int32, device="cuda")
+        outm = torch.empty(c * sectors, dtype=torch.int32, device="cuda")
+        best = {"direct": None, "batch": None}
+        for w, p in candidates(n):
+            try:
+                d = _time(lambda: binding.afps(single, c, 1, 0, out=out1, variant=(w, p)), reps)
+                b = _time(lambda: binding.afps(many, c * sectors, sectors, 0, out=outm, variant=(w, p)),
+                          reps)
+            except binding.AfpsError:
+                continue
+            for kind, ms in (("direct", d), ("batch", b)):
+                if best[kind] is None or ms < best[kind][3]:
+                    best[kind] = (n, w, p, ms)
+        for kind in ("direct", "batch"):
+            if best[kind] is not None:
+                table[kind].append(best[kind])
+                if install:
+                    binding.tune_set(n, best[kind][1], best[kind][2],
+                                     binding.TUNE_DIRECT if kind == "direct" else binding.TUNE_BATCH)
+        if log:
+            log("tune n=%d: direct %s batch %s" % (n, best["direct"], best["batch"]))
+        del single, many
+    if cache_path:
+        with open(cache_path, "w") as f:
+            for kind in ("direct", "batch"):
+                for n, w, p, _ in table[kind]:
+                    f.write("%s %d %d %d\n" % (kind, n, w, p))
+    table["seconds"] = time.perf_counter() - t0
+    return table

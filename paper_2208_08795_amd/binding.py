@@ -247,14 +247,17 @@ def set_spin_limit(polls: int):
     _check(lib().afps_set_spin_limit(polls))
 
 
-def tune_get(n_s: int, k=None):
+TUNE_DIRECT, TUNE_NPDU, TUNE_BATCH = 0, 1, 2
+
+
+def tune_get(n_s: int, kind: int = TUNE_DIRECT):
     w, s = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().afps_tune_get(n_s, -1 if k is None else k, ctypes.byref(w), ctypes.byref(s)))
+    _check(lib().afps_tune_get(n_s, kind, ctypes.byref(w), ctypes.byref(s)))
     return w.value, s.value
 
 
-def tune_set(n_s_max: int, waves: int, slots: int):
-    _check(lib().afps_tune_set(n_s_max, 0, waves, slots))
+def tune_set(n_s_max: int, waves: int, slots: int, kind: int = TUNE_DIRECT):
+    _check(lib().afps_tune_set(n_s_max, kind, waves, slots))
 
 
 def tune_reset():

@@ -94,8 +94,10 @@ const VariantEntry* rule_full(int n) {
 struct Tuned {
     int n_max, waves, slots;
 };
+// Tuned full-update variants: [0] single-cloud (direct) launches, [1] batch
+// plans (persistent launches); each ascending in n_max.
 std::mutex g_tune_mu;
-std::vector<Tuned> g_tuned;   // ascending n_max
+std::vector<Tuned> g_tuned[2];
 bool g_tune_loaded = false;
 
 void load_tune_file_locked() {
@@ -105,23 +107,25 @@ void load_tune_file_locked() {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
+    // lines: "<direct|batch> <n_max> <waves> <slots>"
     char kind[16];
     int n_max, waves, slots;
     while (std::fscanf(f, "%15s %d %d %d", kind, &n_max, &waves, &slots) == 4) {
-        if (std::strcmp(kind, "full") != 0) continue;
+        const int t = std::strcmp(kind, "direct") == 0 ? 0 : std::strcmp(kind, "batch") == 0 ? 1 : -1;
         const VariantEntry* v = find_full(waves, slots);
-        if (v && capacity(*v) >= n_max) g_tuned.push_back({n_max, waves, slots});
+        if (t >= 0 && v && capacity(*v) >= n_max) g_tuned[t].push_back({n_max, waves, slots});
     }
     std::fclose(f);
-    std::sort(g_tuned.begin(), g_tuned.end(),
-              [](const Tuned& a, const Tuned& b) { return a.n_max < b.n_max; });
+    for (auto& tab : g_tuned)
+        std::sort(tab.begin(), tab.end(), [](const Tuned& a, const Tuned& b) { return a.n_max < b.n_max; });
 }
 
-const VariantEntry* choose_full(int n) {
+// Variant for a full-update sector of n points; batch = persistent launch.
+const VariantEntry* choose_full(int n, bool batch = false) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_tune_file_locked();
-        for (const auto& t : g_tuned)
+        for (const auto& t : g_tuned[batch ? 1 : 0])
             if (n <= t.n_max) {
                 const VariantEntry* v = find_full(t.waves, t.slots);
                 if (v && capacity(*v) >= n) return v;
@@ -370,41 +374,42 @@ int afps_afps_variant(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t
     return launch_full_direct(*v, xyz, n, c, m, start, out_idx, (hipStream_t)stream);
 }
 
-int afps_tune_get(int32_t n_s, int32_t k, int32_t* waves, int32_t* slots) {
+int afps_tune_get(int32_t n_s, int32_t kind, int32_t* waves, int32_t* slots) {
     if (!waves || !slots) return fail(AFPS_ERR_NULL, "waves and slots must be non-null");
     if (n_s < 1) return fail(AFPS_ERR_ARG, "n_s must be positive");
-    if (k >= 0) {
+    if (kind == AFPS_TUNE_NPDU) {
         const NpduEntry* v = choose_npdu(n_s);
         if (!v) return fail(AFPS_ERR_UNSUPPORTED, "sector too large");
         *waves = 1;
         *slots = v->chunk64;
         return AFPS_OK;
     }
-    const VariantEntry* v = n_s <= kMaxFullSector ? choose_full(n_s) : nullptr;
+    if (kind != AFPS_TUNE_DIRECT && kind != AFPS_TUNE_BATCH) return fail(AFPS_ERR_ARG, "unknown tuning kind");
+    const VariantEntry* v = n_s <= kMaxFullSector ? choose_full(n_s, kind == AFPS_TUNE_BATCH) : nullptr;
     if (!v) return fail(AFPS_ERR_UNSUPPORTED, "sector too large");
     *waves = v->waves;
     *slots = v->slots;
     return AFPS_OK;
 }
 
-int afps_tune_set(int32_t n_s_max, int32_t npdu, int32_t waves, int32_t slots) {
-    if (npdu) return fail(AFPS_ERR_ARG, "NPDU variants are chosen by sector size only");
+int afps_tune_set(int32_t n_s_max, int32_t kind, int32_t waves, int32_t slots) {
+    if (kind != AFPS_TUNE_DIRECT && kind != AFPS_TUNE_BATCH)
+        return fail(AFPS_ERR_ARG, "only full-update variants are tuned (NPDU uses one wave per sector)");
     const VariantEntry* v = find_full(waves, slots);
     if (!v || capacity(*v) < n_s_max) return fail(AFPS_ERR_ARG, "variant does not exist or is too small");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file_locked();
-    g_tuned.erase(std::remove_if(g_tuned.begin(), g_tuned.end(),
-                                 [&](const Tuned& t) { return t.n_max == n_s_max; }),
-                  g_tuned.end());
-    g_tuned.push_back({n_s_max, waves, slots});
-    std::sort(g_tuned.begin(), g_tuned.end(),
-              [](const Tuned& a, const Tuned& b) { return a.n_max < b.n_max; });
+    auto& tab = g_tuned[kind == AFPS_TUNE_BATCH ? 1 : 0];
+    tab.erase(std::remove_if(tab.begin(), tab.end(), [&](const Tuned& t) { return t.n_max == n_s_max; }),
+              tab.end());
+    tab.push_back({n_s_max, waves, slots});
+    std::sort(tab.begin(), tab.end(), [](const Tuned& a, const Tuned& b) { return a.n_max < b.n_max; });
     return AFPS_OK;
 }
 
 void afps_tune_reset(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned.clear();
+    for (auto& tab : g_tuned) tab.clear();
     g_tune_loaded = true;   // forget the cache file too
 }
 
@@ -501,7 +506,7 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
                 st.lds = npdu_lds_bytes(*v, std::min(cls, capacity(*v)));
                 st.cost = (double)cs * 300.0;   // per-iteration cost roughly independent of n_s
             } else {
-                const VariantEntry* v = ns <= kMaxFullSector ? choose_full(ns) : nullptr;
+                const VariantEntry* v = ns <= kMaxFullSector ? choose_full(ns, true) : nullptr;
                 if (!v)
                     return fail(AFPS_ERR_UNSUPPORTED,
                                 where + "sector of " + std::to_string(ns) +

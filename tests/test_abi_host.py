@@ -59,6 +59,8 @@ def test_host_validation_without_gpu(L):
     assert L.afps_plan_create(ctypes.cast(descs, ctypes.c_void_p), 2, ctypes.byref(plan)) == -2
     assert "descriptor 1" in L.afps_last_error().decode()
     assert L.afps_tune_set(100, 0, 3, 5) == -2   # no such variant
+    assert L.afps_tune_set(100, 1, 1, 1) == -2   # NPDU is not tuned
+    assert L.afps_tune_set(100, 0, 1, 1) == -2   # 64 points: too small for 100
     assert L.afps_max_sector_points() == 32768
 
 
@@ -76,3 +78,27 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         binding.lib()
+
+
+def test_tune_tables_round_trip(L):
+    from paper_2208_08795_amd import binding
+    binding.tune_reset()
+    rule = binding.tune_get(3000, binding.TUNE_DIRECT)
+    assert 64 * rule[0] * rule[1] >= 3000
+    binding.tune_set(4096, 16, 4, binding.TUNE_DIRECT)
+    binding.tune_set(4096, 2, 32, binding.TUNE_BATCH)
+    assert binding.tune_get(3000, binding.TUNE_DIRECT) == (16, 4)
+    assert binding.tune_get(3000, binding.TUNE_BATCH) == (2, 32)
+    assert binding.tune_get(5000, binding.TUNE_DIRECT) == binding.tune_get(5000, binding.TUNE_DIRECT)
+    assert binding.tune_get(3000, binding.TUNE_NPDU) == (1, 1)
+    binding.tune_reset()
+    assert binding.tune_get(3000, binding.TUNE_DIRECT) == rule
+
+
+def test_autotune_candidates_hold_the_class():
+    from paper_2208_08795_amd.autotune import CLASSES, candidates
+    for n in CLASSES:
+        cands = candidates(n)
+        assert cands, n
+        assert all(64 * w * p >= n for w, p in cands)
+    assert (1, 1) in candidates(64) and (16, 32) in candidates(32768)

@@ -233,3 +233,21 @@ def test_grid_barrier_timeout_is_bounded(B, torch_dev):
     f = int(bad[0]) if bad.size else len(got)
     assert np.array_equal(got[:f], want[:f])
     assert np.all(got[f:] == -1)
+
+
+def test_autotuner_choices_stay_exact(B, torch_dev):
+    """The autotuner installs its fastest variants; sampling with them still
+    gives the oracle's indices (direct launches and batch plans)."""
+    torch, dev = torch_dev
+    from paper_2208_08795_amd import autotune
+    try:
+        table = autotune.tune(classes=(256, 3000), reps=1, batch_points=1 << 18, max_iters=64)
+        print("autotune", table, flush=True)
+        assert len(table["direct"]) == 2 and len(table["batch"]) == 2
+        for n in (256, 3000):
+            pts = synth.object_cloud(n, seed=n)
+            _check(B, torch, dev, pts, n // 4, 1, None, 3, label="tuned-direct")
+        clouds = [synth.object_cloud(n, seed=n + 1) for n in (200, 256, 2900, 3000)]
+        _batch_case(B, torch, dev, clouds, [50, 64, 700, 750], [1] * 4, [None] * 4, [0, 1, 2, 3])
+    finally:
+        B.tune_reset()
