@@ -161,6 +161,21 @@ def serving(torch, rates=(50, 200, 800), frames_npdu=160, frames_fps=24, pool=48
     return res
 
 
+def counter_traffic():
+    """HBM bytes per launch of the NPDU step from the committed FETCH_SIZE /
+    WRITE_SIZE runs, or None when the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "persistent_npdu_kernel_batch256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = "".join(open(os.path.join(ROOT, s)).read() for s in rec["sources"])
+    if hashlib.sha256(src.encode()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
     """The oracle (never tuned) on the host cores: one cloud per task."""
     import oracle
@@ -253,7 +268,7 @@ def main():
     hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 32 * plan.items
     res["roofline"] = {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": VALU_PEAK_TOPS,
                        "unit": "TOPS (fp32 VALU ops)", "frac": ops / kern_s / 1e12 / VALU_PEAK_TOPS,
-                       "traffic": None,
+                       "traffic": counter_traffic(),
                        "kernel": "persistent_npdu_kernel<1,true>",
                        "algorithmic_ops_per_launch": ops, "distance_updates_per_launch": upd,
                        "hbm_bytes_per_launch": hbm_bytes,
