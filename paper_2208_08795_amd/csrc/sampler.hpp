@@ -87,6 +87,31 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     v = max(v, dpp_rows<0x143, 0xC>(v));   // row_bcast:31 into rows 2, 3
     return readlane(v, 63);
 }
+// Two independent whole-wave maxima, step by step interleaved so that each
+// chain's DPP hazard wait is filled by the other chain.
+__device__ __forceinline__ void wave_max2(uint32_t a, uint32_t b, uint32_t& ma, uint32_t& mb) {
+    a = max(a, dpp<0xB1>(a));
+    b = max(b, dpp<0xB1>(b));
+    a = max(a, dpp<0x4E>(a));
+    b = max(b, dpp<0x4E>(b));
+    a = max(a, dpp<0x141>(a));
+    b = max(b, dpp<0x141>(b));
+    a = max(a, dpp<0x140>(a));
+    b = max(b, dpp<0x140>(b));
+    a = max(a, dpp_rows<0x142, 0xA>(a));
+    b = max(b, dpp_rows<0x142, 0xA>(b));
+    a = max(a, dpp_rows<0x143, 0xC>(a));
+    b = max(b, dpp_rows<0x143, 0xC>(b));
+    ma = readlane(a, 63);
+    mb = readlane(b, 63);
+}
+// Candidate (distance bits, index) `g, i` replaces (gb, ib) if it is larger,
+// or equal with a lower index.  Branch-free selects.
+__device__ __forceinline__ void take_better(uint32_t g, uint32_t i, uint32_t& gb, uint32_t& ib) {
+    const bool t = g > gb || (g == gb && i < ib);
+    gb = t ? g : gb;
+    ib = t ? i : ib;
+}
 // Whole-wave min, returned wave-uniform (rows outside the mask see UINT_MAX).
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
     v = row_min(v);
@@ -274,15 +299,21 @@ __device__ __forceinline__ void sample_sector(const float* __restrict__ xyz, int
     load_points<P, T, DL>(xyz, n, ns, t, X, Y, Z, D);
 
     float px = xyz[3 * cur + 0], py = xyz[3 * cur + 1], pz = xyz[3 * cur + 2];
-    if (t == 0) out[0] = base + cur;
+    // Picks are buffered one per lane of wave 0 (pick i in lane i mod 64) and
+    // written 64 at a time.
+    uint32_t picks = (uint32_t)(base + cur);
 
     for (int i = 1; i < c; ++i) {
         const Pick mine = update_and_pick<P, T, DL>(ns, w, lane, X, Y, Z, D, px, py, pz);
         const Pick p = combine_waves<W>(mine, lds, i & 1, w, lane);
         cur = (int)p.idx;
         px = p.x; py = p.y; pz = p.z;
-        if (t == 0) out[i] = base + cur;
+        const int slot = i & 63;
+        picks = lane == slot ? (uint32_t)(base + cur) : picks;
+        if (slot == 63 && w == 0) out[i - 63 + lane] = (int32_t)picks;
     }
+    const int tail = (c - 1) & 63;   // picks of the last, partial group
+    if (w == 0 && tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
 }
 
 // NPDU on one sector (Sec. III-C), one wave.
@@ -351,7 +382,9 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
         bi[r] = blk < nb ? (uint32_t)(64 * blk) : 0xFFFFFFFFu;
     }
     const int below = k >> 1, above = k - (k >> 1);
-    if (lane == 0) out[0] = base + cur;
+    // Picks are buffered one per lane (pick i in lane i mod 64) and written
+    // 64 at a time.
+    uint32_t picks = (uint32_t)(base + cur);
 
     for (int i = 1; i < c; ++i) {
         const int lo = max(0, cur - below);
@@ -359,7 +392,8 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
         const int blo = lo >> 6, bhi = hi >> 6;
         const uint32_t span = (uint32_t)(hi - lo);
 
-        // Loads: the sample's coordinates and the first two window blocks.
+        // One round of loads: the sample's coordinates and the first two
+        // window blocks (x, y, z, D).
         const int j0 = 64 * blo + lane, j1 = j0 + 64;
         uint32_t d0 = sd[j0], d1 = sd[j1];
         float px, py, pz, x0, y0, z0, x1, y1, z1;
@@ -374,21 +408,22 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
             x1 = ok1 ? xyz[3 * j1] : 0.f; y1 = ok1 ? xyz[3 * j1 + 1] : 0.f; z1 = ok1 ? xyz[3 * j1 + 2] : 0.f;
         }
 
-        // Best block outside the window's blocks [blo, bhi]: maximum, then the
-        // lowest index.  Independent of the loads above: overlaps them.
-        uint32_t mo = 0u;
+        // Best block outside the window's blocks [blo, bhi] (maximum, then the
+        // lowest index); independent of the loads above, so it runs while
+        // they are in flight.
+        uint32_t g_best, i_best = 0xFFFFFFFFu;
+        {
+            const uint32_t nblk = (uint32_t)(bhi - blo);
+            uint32_t mo = 0u;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t rel = (uint32_t)(64 * r + lane - blo);
-            mo = max(mo, rel > (uint32_t)(bhi - blo) ? bm[r] : 0u);
-        }
-        uint32_t g_best = wave_max(mo);
-        uint32_t i_best = 0xFFFFFFFFu;
+            for (int r = 0; r < R; ++r)
+                mo = max(mo, (uint32_t)(64 * r + lane - blo) > nblk ? bm[r] : 0u);
+            g_best = wave_max(mo);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t rel = (uint32_t)(64 * r + lane - blo);
-            const uint64_t hit = ballot(rel > (uint32_t)(bhi - blo) && bm[r] == g_best);
-            if (i_best == 0xFFFFFFFFu && hit) i_best = readlane(bi[r], (int)__builtin_ctzll(hit));
+            for (int r = 0; r < R; ++r) {
+                const uint64_t hit = ballot((uint32_t)(64 * r + lane - blo) > nblk && bm[r] == g_best);
+                if (i_best == 0xFFFFFFFFu && hit) i_best = readlane(bi[r], (int)__builtin_ctzll(hit));
+            }
         }
 
         // Window update of the two blocks (points outside the window keep D).
@@ -400,21 +435,24 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
             sd[j0] = d0;
             sd[j1] = d1;
         }
-        // Re-reduce both blocks (independent chains interleave); the second
-        // may be the empty padding block, whose candidates lie past n and
-        // never win against a real point.
-        const uint32_t g0 = wave_max(d0), g1 = wave_max(d1);
-        const uint32_t i0 = (uint32_t)(64 * blo) + (uint32_t)__builtin_ctzll(ballot(d0 == g0));
-        const uint32_t i1 = (uint32_t)(64 * blo + 64) + (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+        // Re-reduce both blocks and record them in their lanes.  The second
+        // may be the empty padding block (block nb): it is not recorded, and
+        // its candidates lie past n, so they never beat a real point.
+        {
+            uint32_t g0, g1;
+            wave_max2(d0, d1, g0, g1);
+            const uint32_t i0 = (uint32_t)(64 * blo) + (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+            const uint32_t i1 = (uint32_t)(64 * blo + 64) + (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+            take_better(g0, i0, g_best, i_best);
+            take_better(g1, i1, g_best, i_best);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int blk = 64 * r + lane;
-            bm[r] = blk == blo ? g0 : (blk == blo + 1 && blk < nb ? g1 : bm[r]);
-            bi[r] = blk == blo ? i0 : (blk == blo + 1 && blk < nb ? i1 : bi[r]);
+            for (int r = 0; r < R; ++r) {
+                const int blk = 64 * r + lane;
+                const bool second = blk == blo + 1 && blk < nb;
+                bm[r] = blk == blo ? g0 : (second ? g1 : bm[r]);
+                bi[r] = blk == blo ? i0 : (second ? i1 : bi[r]);
+            }
         }
-        if (g0 > g_best || (g0 == g_best && i0 < i_best)) { g_best = g0; i_best = i0; }
-        if (g1 > g_best || (g1 == g_best && i1 < i_best)) { g_best = g1; i_best = i1; }
-
         // Windows wider than two blocks (k > 64): the remaining blocks.
         for (int b = blo + 2; b <= bhi; ++b) {
             const int j = 64 * b + lane;
@@ -428,17 +466,21 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
             }
             const uint32_t g = wave_max(d);
             const uint32_t idx = (uint32_t)(64 * b) + (uint32_t)__builtin_ctzll(ballot(d == g));
+            take_better(g, idx, g_best, i_best);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int blk = 64 * r + lane;
                 bm[r] = blk == b ? g : bm[r];
                 bi[r] = blk == b ? idx : bi[r];
             }
-            if (g > g_best || (g == g_best && idx < i_best)) { g_best = g; i_best = idx; }
         }
         cur = (int)i_best;
-        if (lane == 0) out[i] = base + cur;
+        const int slot = i & 63;
+        picks = lane == slot ? (uint32_t)(base + cur) : picks;
+        if (slot == 63) out[i - 63 + lane] = (int32_t)picks;
     }
+    const int tail = (c - 1) & 63;   // picks of the last, partial group
+    if (tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
 }
 
 }  // namespace afps
