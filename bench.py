@@ -120,6 +120,49 @@ def single_cloud_latency(torch, binding, synth, stream, reps=20):
     return res
 
 
+CLOCK_GHZ = 2.4   # MI355X peak engine clock (SQ counters measured 2.41 GHz under these kernels)
+
+
+def config2_sweep(torch, binding, synth, stream, reps=10):
+    """Object cloud N=8192, C=2048: plain FPS, AFPS for M in {1..32}, NPDU at
+    k in {8, 32, 128}: time per call (median), cycles per iteration of the
+    longest sector, coverage radius relative to plain FPS."""
+    from paper_2208_08795_amd.quality import coverage_radius
+    pts = synth.object_cloud(8192, 0)
+    xyz = torch.from_numpy(pts).cuda()
+    out = torch.empty(2048, dtype=torch.int32, device="cuda")
+    rows = []
+    ref = None
+    for m in (1, 2, 4, 8, 16, 32):
+        for k in (None, 8, 32, 128):
+            def run():
+                if k is None:
+                    binding.afps(xyz, 2048, m, 0, out=out, stream=stream)
+                else:
+                    binding.afps_npdu(xyz, 2048, m, k, 0, out=out, stream=stream)
+            run()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                run()
+                b.record(stream)
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            ms = float(np.median(ts))
+            r = coverage_radius(pts, out.cpu().numpy())
+            if m == 1 and k is None:
+                ref = r
+            iters = -(-2048 // m) - 1
+            rows.append({"m": m, "k": k, "ms": round(ms, 4), "sampled_pts_per_s": 2048 / (ms / 1e3),
+                         "cycles_per_iteration": round(ms * 1e-3 * CLOCK_GHZ * 1e9 / iters, 1),
+                         "coverage_radius": round(r, 5), "coverage_vs_fps": round(r / ref, 4)})
+    log("config-2 sweep: " + ", ".join("M%d/k%s %.3fms r%.2f" % (x["m"], x["k"], x["ms"], x["coverage_vs_fps"])
+                                       for x in rows))
+    return rows
+
+
 def serving(torch, rates=(50, 200, 800), frames_npdu=160, frames_fps=24, pool=48, seed=1):
     """Open-loop Poisson streams of LiDAR frames (N uniform in [16384, 131072],
     C = N/8, M in {8, 16, 32}, k = 64) through the continuous-batching server,
@@ -307,7 +350,13 @@ def main():
         fplan.close()
 
     if not args.no_single:
-        res["single_cloud_ms"] = single_cloud_latency(torch, binding, synth, stream)
+        single = single_cloud_latency(torch, binding, synth, stream)
+        res["single_cloud_ms"] = single
+        iters = {"cfg1_fps_n2048_c512": 511, "cfg3_fps_n32768_c8192": 8191, "cfg3_afps_npdu_m16_k64": 511,
+                 "cfg2_afps_m32_n8192_c2048": 63, "cfg2_afps_npdu_m32_k32": 63, "cfg2_fps_n8192_c2048": 2047}
+        res["cycles_per_iteration"] = {k: round(v * 1e-3 * CLOCK_GHZ * 1e9 / iters[k], 1) for k, v in single.items()}
+        res["cycles_per_iteration"]["note"] = "call time x 2.4 GHz / iterations of the longest sector (launch included)"
+        res["config2_sweep"] = config2_sweep(torch, binding, synth, stream)
 
     if not args.no_serve:
         res["serving"] = serving(torch)

@@ -50,7 +50,9 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
     load_points<P, T, false>(xyz + 3 * (int64_t)first, cnt, ns, t, X, Y, Z, D);
     float px = xyz[3 * (int64_t)start + 0], py = xyz[3 * (int64_t)start + 1],
           pz = xyz[3 * (int64_t)start + 2];
-    if (g == 0 && t == 0) out[0] = start;
+    // Picks are buffered one per lane (pick i in lane i mod 64); wave 0 of
+    // workgroup 0 writes them 64 at a time.
+    uint32_t picks = (uint32_t)start;
 
     for (int i = 1; i < c; ++i) {
         const Pick mine = update_and_pick<P, T, false>(ns, w, lane, X, Y, Z, D, px, py, pz);
@@ -77,8 +79,11 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
         }
         __syncthreads();
         if (!go) {
-            if (g == 0)
+            if (g == 0) {
+                const int done = i & ~63;   // picks before `done` are written
+                if (w == 0 && lane < (i & 63)) out[done + lane] = (int32_t)picks;
                 for (int j = i + t; j < c; j += T) out[j] = -1;
+            }
             return;
         }
         // Acquire in every wave before reading the other workgroups' slots.
@@ -99,8 +104,12 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
         }
         const int cur = (int)readlane(li, win);
         px = readlane(lx, win); py = readlane(ly, win); pz = readlane(lz, win);
-        if (g == 0 && t == 0) out[i] = cur;
+        const int slot = i & 63;
+        picks = lane == slot ? (uint32_t)cur : picks;
+        if (slot == 63 && g == 0 && w == 0) out[i - 63 + lane] = (int32_t)picks;
     }
+    const int tail = (c - 1) & 63;   // picks of the last, partial group
+    if (g == 0 && w == 0 && tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
 }
 
 __global__ void grid_reset(GridSync* gs) {
