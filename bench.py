@@ -286,6 +286,11 @@ def main():
     calib2 = torch.empty_like(calib)
     calib2.copy_(calib)
 
+    if not args.no_tune:
+        from paper_2208_08795_amd import autotune
+        log("autotuning the batch plan's wave budget")
+        occ = autotune.tune_occupancy(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256, log=log)
+        res_occ = [[f, round(t, 4)] for f, t in occ]
     plan = binding.BatchPlan(sizes, cs, [M] * 256, [K] * 256, [0] * 256, device=dev)
     out = torch.empty(plan.total_samples, dtype=torch.int32, device=dev)
     log("AFPS-NPDU plan: %d items, %d launch(es)" % (plan.items, plan.launches))
@@ -302,13 +307,15 @@ def main():
                                   "C = N/4 (%d samples), AFPS M=8 with NPDU k=32, one persistent launch "
                                   "per step replayed from a hipGraph" % (sum(sizes), total_samples),
                       "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples}}
+    if not args.no_tune:
+        res["plan_occupancy_tuning"] = {"waves_per_simd_vs_ms": res_occ, "chosen": res_occ[0][0]}
     res["batch_latency"] = {"unit": "ms", "what": "per step (whole batch of 256 clouds), HIP events",
                             "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
 
     # Roofline of the dominant kernel (the persistent NPDU kernel is the step).
     ops, upd = npdu_work(sizes, cs, out_np, plan.offsets, M, K)
     kern_s = float(np.mean(ev_ms)) / 1e3
-    hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 32 * plan.items
+    hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
     res["roofline"] = {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": VALU_PEAK_TOPS,
                        "unit": "TOPS (fp32 VALU ops)", "frac": ops / kern_s / 1e12 / VALU_PEAK_TOPS,
                        "traffic": counter_traffic(),

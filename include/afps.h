@@ -117,6 +117,14 @@ int afps_plan_create(const afps_cloud_desc *descs, int32_t batch, afps_plan **pl
 size_t afps_plan_workspace_bytes(const afps_plan *plan);
 
 /*
+ * Workspace bytes of a plan with `items` work items in total (one per sector,
+ * i.e. the sum of m over the batch): queue counters plus the item table,
+ * rounded up to 256.  Lets a caller reserve device memory before building
+ * the plan.  Host-only arithmetic; 0 for items <= 0.
+ */
+size_t afps_workspace_bytes_for_items(int32_t items);
+
+/*
  * Copy the plan's work-item table into `workspace` (DEVICE, >= the size
  * above, 256-byte aligned) on `stream`.  Must precede afps_plan_launch with
  * that workspace; the table stays valid until overwritten.
@@ -180,6 +188,15 @@ void afps_tune_reset(void);
 int afps_afps_variant(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
                       int32_t start, int32_t *out_idx, int32_t waves, int32_t slots,
                       void *stream);
+
+/*
+ * Wave budget of batch plans created afterwards, in waves per SIMD (default
+ * 1): the persistent grids of a plan are sized from its longest work item
+ * (the critical path) and each bucket's total work so that together they
+ * keep about this many waves per SIMD.  Process-wide; AFPS_ERR_ARG outside
+ * (0, 64].
+ */
+int afps_set_plan_occupancy(float waves_per_simd);
 
 /*
  * Bound on the polls of one grid-barrier wait in the multi-workgroup plain-FPS

@@ -95,3 +95,28 @@ def tune(classes=CLASSES, reps: int = 3, batch_points: int = 1 << 22, max_iters:
                     f.write("%s %d %d %d\n" % (kind, n, w, p))
     table["seconds"] = time.perf_counter() - t0
     return table
+
+
+def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 64.0),
+                   reps: int = 5, install: bool = True, log=None):
+    """Sector-to-CU mapping of batch plans: time the batch's persistent launches
+    under several wave budgets (waves per SIMD; 64 = as many workgroups as fit)
+    and keep the fastest.  Returns [(factor, ms)], best first."""
+    import torch
+
+    from . import binding
+    res = []
+    for f in factors:
+        binding.set_plan_occupancy(f)
+        plan = binding.BatchPlan(sizes, cs, ms, ks, starts, device=xyz_all.device)
+        out = torch.empty(plan.total_samples, dtype=torch.int32, device=xyz_all.device)
+        plan.launch(xyz_all, out_all=out, graph=True)
+        ms_ = _time(lambda: plan.launch(xyz_all, out_all=out, graph=True), reps)
+        torch.cuda.synchronize()
+        plan.close()
+        res.append((f, ms_))
+        if log:
+            log("plan occupancy %.1f waves/SIMD: %.4f ms" % (f, ms_))
+    res.sort(key=lambda x: x[1])
+    binding.set_plan_occupancy(res[0][0] if install else 1.0)
+    return res

@@ -58,6 +58,7 @@ def lib():
             "afps_max_sector_points": ([], i32),
             "afps_plan_create": ([vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
             "afps_plan_workspace_bytes": ([vp], sz),
+            "afps_workspace_bytes_for_items": ([i32], sz),
             "afps_plan_upload": ([vp, vp, sz, vp], ctypes.c_int),
             "afps_plan_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
             "afps_plan_graph_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
@@ -70,6 +71,7 @@ def lib():
             "afps_tune_set": ([i32, i32, i32, i32], ctypes.c_int),
             "afps_tune_reset": ([], None),
             "afps_set_spin_limit": ([ctypes.c_uint32], ctypes.c_int),
+            "afps_set_plan_occupancy": ([ctypes.c_float], ctypes.c_int),
             "afps_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "afps_last_error": ([], ctypes.c_char_p),
         }
@@ -241,6 +243,15 @@ def batched(clouds, cs, ms, ks, starts=None, graph=False, stream=None):
     torch.cuda.current_stream().synchronize()
     plan.close()
     return res
+
+
+def workspace_bytes_for_items(items: int) -> int:
+    """Device workspace of a batch plan with `items` sectors in total."""
+    return int(lib().afps_workspace_bytes_for_items(items))
+
+
+def set_plan_occupancy(waves_per_simd: float):
+    _check(lib().afps_set_plan_occupancy(waves_per_simd))
 
 
 def set_spin_limit(polls: int):

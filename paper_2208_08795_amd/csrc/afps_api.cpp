@@ -236,6 +236,11 @@ int launch_npdu_direct(const NpduEntry& v, const float* xyz, int32_t n, int32_t 
 
 unsigned g_spin_limit = 1u << 22;
 
+// Persistent grids of a plan are sized so that together they keep about this
+// many waves per SIMD (1 = every wave has a SIMD to itself, so the longest
+// sectors run at their full single-wave speed).
+float g_waves_per_simd = 1.0f;
+
 int launch_grid_fps(const float* xyz, int32_t n, int32_t c, int32_t start, int32_t* out,
                      hipStream_t stream) {
     const GridVariant* gv = nullptr;
@@ -413,6 +418,13 @@ void afps_tune_reset(void) {
     g_tune_loaded = true;   // forget the cache file too
 }
 
+int afps_set_plan_occupancy(float waves_per_simd) {
+    if (!(waves_per_simd > 0.0f) || waves_per_simd > 64.0f)
+        return fail(AFPS_ERR_ARG, "waves per SIMD must be in (0, 64]");
+    g_waves_per_simd = waves_per_simd;
+    return AFPS_OK;
+}
+
 int afps_set_spin_limit(uint32_t polls) {
     if (polls == 0) return fail(AFPS_ERR_ARG, "spin limit must be positive");
     g_spin_limit = polls;
@@ -431,8 +443,10 @@ struct Bucket {
     int lds_bytes;        // dynamic LDS
     int first, count;     // items [first, first + count) of the plan
     int grid;             // workgroups launched
-    double cost;          // estimated work, for ordering
+    double cost;          // estimated work (cycles of one workgroup), for ordering and sizing
+    double longest;       // estimated cycles of the bucket's longest item
 };
+
 
 constexpr size_t kCounterBytes = 256;   // queue counters, one per bucket
 constexpr int kMaxBuckets = (int)(kCounterBytes / sizeof(unsigned));
@@ -499,12 +513,12 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
                 if (!v) return fail(AFPS_ERR_UNSUPPORTED, where + "NPDU sector too large");
                 st.kernel = v->persistent;
                 st.block = 64;
+                st.cost = (double)cs * 950.0;   // cycles per NPDU iteration, nearly independent of n_s
                 // LDS size classes (sectors of <= 512, 1024, 2048, 4096... points):
                 // small sectors keep many workgroups resident per CU.
                 int cls = 512;
                 while (cls < ns) cls *= 2;
                 st.lds = npdu_lds_bytes(*v, std::min(cls, capacity(*v)));
-                st.cost = (double)cs * 300.0;   // per-iteration cost roughly independent of n_s
             } else {
                 const VariantEntry* v = ns <= kMaxFullSector ? choose_full(ns, true) : nullptr;
                 if (!v)
@@ -514,7 +528,11 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
                 st.kernel = v->persistent;
                 st.block = 64 * v->waves;
                 st.lds = v->lds_bytes;
-                st.cost = (double)cs * (double)ns / 64.0 + (double)cs * 100.0;
+                // per iteration: 12 VALU ops per slot on each of the ceil(W/4)
+                // waves sharing a SIMD (4 cycles each), plus the reduction
+                // and, for W > 1, the LDS exchange
+                const int per_simd = (v->waves + 3) / 4;
+                st.cost = (double)cs * (48.0 * v->slots * per_simd + (v->waves > 1 ? 600.0 : 250.0));
             }
             staged.push_back(st);
         }
@@ -528,7 +546,7 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     });
     for (size_t i = 0; i < staged.size();) {
         size_t j = i;
-        Bucket bk{staged[i].kernel, staged[i].block, staged[i].lds, (int)i, 0, 0, 0.0};
+        Bucket bk{staged[i].kernel, staged[i].block, staged[i].lds, (int)i, 0, 0, 0.0, staged[i].cost};
         while (j < staged.size() && staged[j].kernel == bk.kernel && staged[j].lds == bk.lds_bytes) {
             bk.cost += staged[j].cost;
             ++j;
@@ -558,11 +576,33 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         int rc = device_state(&ds);
         if (rc) return rc;
         AFPS_HIP(hipGetDevice(&plan->device));
-        for (auto& bk : plan->buckets) {
+        // Makespan model: a bucket with g workgroups ends after about
+        // max(longest item, work / g) (longest-first queue).  Take the
+        // critical path T = the longest item of the plan, give each bucket
+        // the workgroups it needs to finish by T, and raise T until all
+        // buckets together stay within the wave budget (waves per SIMD x
+        // SIMDs).  Never more workgroups than items or than fit.
+        const double budget = std::max(1.0, (double)g_waves_per_simd * 4.0 * ds->cu_count);
+        std::vector<int> cap(plan->buckets.size());
+        double T = 0.0;
+        for (size_t b = 0; b < plan->buckets.size(); ++b) {
+            Bucket& bk = plan->buckets[b];
             int per_cu = 0;
             AFPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bk.kernel, bk.block, bk.lds_bytes));
             if (per_cu < 1) return fail(AFPS_ERR_UNSUPPORTED, "a kernel variant cannot be resident");
-            bk.grid = std::min(bk.count, per_cu * ds->cu_count);
+            cap[b] = std::min(bk.count, per_cu * ds->cu_count);
+            T = std::max(T, bk.longest);
+        }
+        for (int round = 0; round < 200; ++round) {
+            double waves = 0.0;
+            for (size_t b = 0; b < plan->buckets.size(); ++b) {
+                Bucket& bk = plan->buckets[b];
+                const int g = (int)std::min<double>(cap[b], std::max(1.0, std::ceil(bk.cost / T)));
+                bk.grid = g;
+                waves += (double)g * (bk.block / 64);
+            }
+            if (waves <= budget) break;
+            T *= 1.05;
         }
         if (plan->buckets.size() > 1) {
             int hrc = helper_streams(ds);   // created outside any stream capture
@@ -575,13 +615,18 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             plan->events.push_back(e);
         }
     }
-    plan->ws_bytes = kCounterBytes + plan->items.size() * sizeof(WorkItem);
-    plan->ws_bytes = (plan->ws_bytes + 255) / 256 * 256;
+    plan->ws_bytes = afps_workspace_bytes_for_items((int32_t)plan->items.size());
     *plan_out = plan.release();
     return AFPS_OK;
 }
 
 size_t afps_plan_workspace_bytes(const afps_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+size_t afps_workspace_bytes_for_items(int32_t items) {
+    if (items <= 0) return 0;
+    const size_t b = kCounterBytes + (size_t)items * sizeof(WorkItem);
+    return (b + 255) / 256 * 256;
+}
 int32_t afps_plan_items(const afps_plan* plan) { return plan ? (int32_t)plan->items.size() : 0; }
 int32_t afps_plan_launches(const afps_plan* plan) { return plan ? (int32_t)plan->buckets.size() : 0; }
 

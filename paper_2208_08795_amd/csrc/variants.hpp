@@ -8,7 +8,7 @@
 
 namespace afps {
 
-// One sector's work, as the batch queue hands it out (32 bytes).
+// One sector's work, as the batch queue hands it out (40 bytes).
 struct WorkItem {
     int64_t xyz_offset;   // first point of the sector, in points, into xyz_all
     int64_t out_offset;   // first output of the sector, in indices, into out_all
@@ -19,6 +19,7 @@ struct WorkItem {
     int32_t base;         // index of the sector's first point inside its cloud
     int32_t pad;
 };
+static_assert(sizeof(WorkItem) == 40, "work item layout");
 
 // Full-update sector kernels (kernels.hip): W waves, P slots per thread.
 struct VariantEntry {

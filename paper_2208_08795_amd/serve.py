@@ -86,15 +86,22 @@ class Request:
         return None if self.done is None else self.done - self.arrival
 
 
-def footprint(req: Request) -> tuple[int, int, int]:
-    """(points bytes, output bytes, workspace bytes) a frame needs on the device."""
-    return 12 * req.n, 4 * req.c, 32 * req.m
+def footprint(req: Request) -> tuple[int, int]:
+    """(points bytes, output bytes) a frame needs on the device."""
+    return 12 * req.n, 4 * req.c
+
+
+def library_workspace_bytes(items: int) -> int:
+    """Workspace of a batch plan with `items` sectors, as the library sizes it."""
+    from . import binding
+    return binding.workspace_bytes_for_items(items)
 
 
 @dataclass
 class Batch:
     requests: list
     ws_off: int = None
+    ws_bytes: int = 0          # size of the arena block reserved for the plan's workspace
     handle: object = None
     launched: float = None
 
@@ -103,8 +110,9 @@ class Scheduler:
     """Admission by HBM footprint, continuous batching, bounded launches in flight."""
 
     def __init__(self, executor, arena_bytes: int, max_inflight: int = 8, max_batch: int = 64,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, workspace_bytes=library_workspace_bytes):
         self.ex = executor
+        self.workspace_bytes = workspace_bytes   # items -> bytes of a plan's workspace
         self.arena = Arena(arena_bytes)
         self.max_inflight = max_inflight
         self.max_batch = max_batch
@@ -116,8 +124,9 @@ class Scheduler:
         self.peak_waiting = 0
 
     def _fits_ever(self, req) -> bool:
-        p, o, w = footprint(req)
-        blocks = sum(-(-x // ALIGN) * ALIGN for x in (p, o)) + -(-(256 + w) // ALIGN) * ALIGN
+        p, o = footprint(req)
+        w = self.workspace_bytes(req.m)
+        blocks = sum(-(-x // ALIGN) * ALIGN for x in (p, o, w))
         return blocks <= self.arena.size
 
     def submit(self, req: Request):
@@ -133,12 +142,11 @@ class Scheduler:
     def _admit(self, now):
         if len(self.inflight) >= self.max_inflight or not self.waiting:
             return None
-        batch, taken = [], 0
-        ws_need = 256
+        batch, taken, items = [], 0, 0
         for req in self.waiting:                     # FIFO: stop at the first that does not fit
             if len(batch) >= self.max_batch:
                 break
-            p, o, w = footprint(req)
+            p, o = footprint(req)
             po = self.arena.alloc(p)
             if po is None:
                 break
@@ -148,28 +156,30 @@ class Scheduler:
                 break
             req.pts_off, req.out_off = po, oo
             batch.append(req)
-            ws_need += w
+            items += req.m
             taken += 1
         if not batch:
             return None
+        # The plan's workspace (queue counters + one work item per sector),
+        # sized exactly as the library sizes it.
+        ws_need = self.workspace_bytes(items)
         ws = self.arena.alloc(ws_need)
-        if ws is None:                                # give the last frame back and retry smaller
-            while batch and ws is None:
-                last = batch.pop()
-                self.arena.free(last.pts_off)
-                self.arena.free(last.out_off)
-                last.pts_off = last.out_off = None
-                ws_need -= footprint(last)[2]
-                taken -= 1
-                if batch:
-                    ws = self.arena.alloc(ws_need)
+        while ws is None:                             # give the last frame back and retry smaller
+            last = batch.pop()
+            self.arena.free(last.pts_off)
+            self.arena.free(last.out_off)
+            last.pts_off = last.out_off = None
+            items -= last.m
+            taken -= 1
             if not batch:
                 return None
+            ws_need = self.workspace_bytes(items)
+            ws = self.arena.alloc(ws_need)
         del self.waiting[:taken]
         for req in batch:
             req.state, req.admitted = "running", now
         self.peak_bytes = max(self.peak_bytes, self.arena.bytes_used)
-        return Batch(batch, ws)
+        return Batch(batch, ws, self.arena.used[ws])
 
     def _release(self, batch: Batch):
         for req in batch.requests:
@@ -272,8 +282,9 @@ class GpuExecutor:
                                                  ctypes.byref(h)))
                 plan = h
                 ws = ctypes.c_void_p(self.base + batch.ws_off)
-                need = int(self.L.afps_plan_workspace_bytes(h))
-                B._check(self.L.afps_plan_upload(h, ws, need, sh))
+                # the true size of the reserved block: the library refuses a
+                # plan whose workspace would not fit in it
+                B._check(self.L.afps_plan_upload(h, ws, batch.ws_bytes, sh))
                 B._check(self.L.afps_plan_launch(h, ctypes.c_void_p(self.base),
                                                  ctypes.c_void_p(self.base), ws, sh))
             for r in fps:

@@ -2,7 +2,7 @@
 admission by footprint, FIFO order, slot reuse, rejection and launch failure."""
 import random
 
-from paper_2208_08795_amd.serve import ALIGN, Arena, Request, Scheduler, footprint
+from paper_2208_08795_amd.serve import ALIGN, Arena, Request, Scheduler, footprint, library_workspace_bytes
 
 
 class FakeClock:
@@ -25,6 +25,9 @@ class FakeExecutor:
     def launch(self, batch):
         if any(r.rid in self.fail_ids for r in batch.requests):
             raise RuntimeError("forced launch failure")
+        # the reserved workspace block holds the plan the library would build
+        items = sum(r.m for r in batch.requests)
+        assert batch.ws_bytes >= library_workspace_bytes(items), (batch.ws_bytes, items)
         self.launched.append([r.rid for r in batch.requests])
         return self.clock.t + 1e-3 * len(batch.requests)
 
@@ -95,10 +98,24 @@ def test_launch_failure_frees_memory_and_others_complete():
 def test_slots_are_reused_under_a_small_budget():
     clock = FakeClock()
     ex = FakeExecutor(clock)
-    one = sum(-(-x // ALIGN) * ALIGN for x in footprint(_req(0, 60000, 0))[:2]) + 2 * ALIGN
+    one = sum(-(-x // ALIGN) * ALIGN for x in footprint(_req(0, 60000, 0))) + 2 * ALIGN
     s = Scheduler(ex, one + ALIGN, max_inflight=4, clock=clock)   # room for one frame at a time
     reqs = [_req(i, 60000, 0.0) for i in range(5)]
     done = s.run(reqs)
     assert all(r.state == "done" for r in done)
     assert all(len(b) == 1 for b in ex.launched) and len(ex.launched) == 5
     assert s.peak_waiting >= 4
+
+
+def test_workspace_block_covers_large_batches():
+    """Regression: the workspace block reserved for a batch must hold the
+    library's item table (40-byte items) for every sector of every frame,
+    also for batches of many 32-sector frames."""
+    clock = FakeClock()
+    ex = FakeExecutor(clock)
+    s = Scheduler(ex, 64 << 20, max_inflight=2, max_batch=32, clock=clock)
+    reqs = [_req(i, 20000, 0.0, m=32) for i in range(64)]
+    done = s.run(reqs)
+    assert all(r.state == "done" for r in done)
+    assert max(len(b) for b in ex.launched) >= 16
+    assert library_workspace_bytes(32 * 16) > 256 + 32 * 32 * 16     # 40 bytes per sector
