@@ -334,6 +334,7 @@ def main():
         res["autotune"]["seconds"] = round(tab["seconds"], 2)
 
     if not args.no_fps:
+        binding.set_plan_occupancy(0.0)      # plain FPS: grids as large as fit
         fplan = binding.BatchPlan(sizes, cs, [1] * 256, [None] * 256, [0] * 256, device=dev)
         fout = torch.empty(fplan.total_samples, dtype=torch.int32, device=dev)
         fsteps = max(3, args.steps // 4)

@@ -190,11 +190,12 @@ int afps_afps_variant(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t
                       void *stream);
 
 /*
- * Wave budget of batch plans created afterwards, in waves per SIMD (default
- * 1): the persistent grids of a plan are sized from its longest work item
- * (the critical path) and each bucket's total work so that together they
- * keep about this many waves per SIMD.  Process-wide; AFPS_ERR_ARG outside
- * (0, 64].
+ * Wave budget of batch plans created afterwards, in waves per SIMD.  0 (the
+ * default) = no budget: each persistent grid is as large as stays resident,
+ * at most one workgroup per work item.  With a budget, each bucket gets the
+ * fewest workgroups whose longest-first schedule of its estimated item costs
+ * ends by the plan's longest item, raised until all grids together keep about
+ * this many waves per SIMD.  Process-wide; AFPS_ERR_ARG outside [0, 64].
  */
 int afps_set_plan_occupancy(float waves_per_simd);
 

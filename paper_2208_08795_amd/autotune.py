@@ -97,11 +97,12 @@ def tune(classes=CLASSES, reps: int = 3, batch_points: int = 1 << 22, max_iters:
     return table
 
 
-def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 64.0),
+def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.0, 1.0, 2.0, 4.0),
                    reps: int = 5, install: bool = True, log=None):
     """Sector-to-CU mapping of batch plans: time the batch's persistent launches
-    under several wave budgets (waves per SIMD; 64 = as many workgroups as fit)
-    and keep the fastest.  Returns [(factor, ms)], best first."""
+    under several wave budgets (waves per SIMD; 0 = no budget, as many
+    workgroups as fit) and keep the fastest.  Returns [(factor, ms)], best
+    first."""
     import torch
 
     from . import binding
@@ -118,5 +119,5 @@ def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.5, 1.0, 1.5, 2
         if log:
             log("plan occupancy %.1f waves/SIMD: %.4f ms" % (f, ms_))
     res.sort(key=lambda x: x[1])
-    binding.set_plan_occupancy(res[0][0] if install else 1.0)
+    binding.set_plan_occupancy(res[0][0] if install else 0.0)
     return res

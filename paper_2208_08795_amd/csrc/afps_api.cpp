@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -236,10 +237,10 @@ int launch_npdu_direct(const NpduEntry& v, const float* xyz, int32_t n, int32_t 
 
 unsigned g_spin_limit = 1u << 22;
 
-// Persistent grids of a plan are sized so that together they keep about this
-// many waves per SIMD (1 = every wave has a SIMD to itself, so the longest
-// sectors run at their full single-wave speed).
-float g_waves_per_simd = 1.0f;
+// Optional wave budget of batch plans, in waves per SIMD; 0 = none (every
+// persistent grid is as large as fits, at most one workgroup per item, which
+// measured fastest on the batched workloads).
+float g_waves_per_simd = 0.0f;
 
 int launch_grid_fps(const float* xyz, int32_t n, int32_t c, int32_t start, int32_t* out,
                      hipStream_t stream) {
@@ -419,8 +420,8 @@ void afps_tune_reset(void) {
 }
 
 int afps_set_plan_occupancy(float waves_per_simd) {
-    if (!(waves_per_simd > 0.0f) || waves_per_simd > 64.0f)
-        return fail(AFPS_ERR_ARG, "waves per SIMD must be in (0, 64]");
+    if (!(waves_per_simd >= 0.0f) || waves_per_simd > 64.0f)
+        return fail(AFPS_ERR_ARG, "waves per SIMD must be 0 (no budget) or in (0, 64]");
     g_waves_per_simd = waves_per_simd;
     return AFPS_OK;
 }
@@ -560,11 +561,15 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     std::sort(plan->buckets.begin(), plan->buckets.end(),
               [](const Bucket& a, const Bucket& b) { return a.cost > b.cost; });
     plan->items.reserve(staged.size());
+    std::vector<double> item_cost(staged.size());   // estimated cycles, aligned with items
     {
         std::vector<WorkItem> ordered(staged.size());
         int pos = 0;
         for (auto& bk : plan->buckets) {
-            for (int i = 0; i < bk.count; ++i) ordered[pos + i] = staged[bk.first + i].item;
+            for (int i = 0; i < bk.count; ++i) {
+                ordered[pos + i] = staged[bk.first + i].item;
+                item_cost[pos + i] = staged[bk.first + i].cost;
+            }
             bk.first = pos;
             pos += bk.count;
         }
@@ -576,12 +581,14 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         int rc = device_state(&ds);
         if (rc) return rc;
         AFPS_HIP(hipGetDevice(&plan->device));
-        // Makespan model: a bucket with g workgroups ends after about
-        // max(longest item, work / g) (longest-first queue).  Take the
-        // critical path T = the longest item of the plan, give each bucket
-        // the workgroups it needs to finish by T, and raise T until all
-        // buckets together stay within the wave budget (waves per SIMD x
-        // SIMDs).  Never more workgroups than items or than fit.
+        // Makespan model: the queue hands out items longest first, so a
+        // bucket run by g workgroups finishes when the longest-processing-
+        // time (LPT) schedule of its item costs on g machines does.  Take
+        // the critical path T = the longest item of the plan, give each
+        // bucket the fewest workgroups whose LPT schedule ends by T, and
+        // raise T until all buckets together stay within the wave budget
+        // (waves per SIMD x SIMDs).  Never more workgroups than items or
+        // than fit.
         const double budget = std::max(1.0, (double)g_waves_per_simd * 4.0 * ds->cu_count);
         std::vector<int> cap(plan->buckets.size());
         double T = 0.0;
@@ -593,16 +600,42 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             cap[b] = std::min(bk.count, per_cu * ds->cu_count);
             T = std::max(T, bk.longest);
         }
-        for (int round = 0; round < 200; ++round) {
-            double waves = 0.0;
-            for (size_t b = 0; b < plan->buckets.size(); ++b) {
-                Bucket& bk = plan->buckets[b];
-                const int g = (int)std::min<double>(cap[b], std::max(1.0, std::ceil(bk.cost / T)));
-                bk.grid = g;
-                waves += (double)g * (bk.block / 64);
+        auto lpt_makespan = [&](const Bucket& bk, int g) {
+            std::vector<double> load(g, 0.0);   // min-heap of machine loads
+            double span = 0.0;
+            for (int i = 0; i < bk.count; ++i) {
+                std::pop_heap(load.begin(), load.end(), std::greater<double>());
+                load.back() += item_cost[bk.first + i];
+                span = std::max(span, load.back());
+                std::push_heap(load.begin(), load.end(), std::greater<double>());
             }
-            if (waves <= budget) break;
-            T *= 1.05;
+            return span;
+        };
+        auto workgroups_for = [&](size_t b, double T) {
+            const Bucket& bk = plan->buckets[b];
+            int lo = (int)std::min<double>(cap[b], std::max(1.0, std::ceil(bk.cost / T)));
+            int hi = cap[b];
+            if (lpt_makespan(bk, lo) <= T * 1.0001) return lo;
+            while (lo + 1 < hi) {                 // smallest g in (lo, hi] meeting T
+                const int mid = lo + (hi - lo) / 2;
+                if (lpt_makespan(bk, mid) <= T * 1.0001) hi = mid;
+                else lo = mid;
+            }
+            return hi;
+        };
+        if (g_waves_per_simd <= 0.0f) {
+            for (size_t b = 0; b < plan->buckets.size(); ++b) plan->buckets[b].grid = cap[b];
+        } else {
+            for (int round = 0; round < 200; ++round) {
+                double waves = 0.0;
+                for (size_t b = 0; b < plan->buckets.size(); ++b) {
+                    Bucket& bk = plan->buckets[b];
+                    bk.grid = workgroups_for(b, T);
+                    waves += (double)bk.grid * (bk.block / 64);
+                }
+                if (waves <= budget) break;
+                T *= 1.05;
+            }
         }
         if (plan->buckets.size() > 1) {
             int hrc = helper_streams(ds);   // created outside any stream capture
