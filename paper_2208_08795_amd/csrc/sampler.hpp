@@ -349,7 +349,22 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
 
     if constexpr (XYZ_IN_LDS) {
         int j = lane;
-        for (; j + 192 < np; j += 256) {          // four points in flight per lane
+        for (; j + 15 * 64 < np; j += 16 * 64) {  // sixteen points in flight per lane
+            float v[48];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int jj = j + 64 * u;
+                const bool ok = jj < n;
+                v[3 * u] = ok ? xyz[3 * jj] : 0.f;
+                v[3 * u + 1] = ok ? xyz[3 * jj + 1] : 0.f;
+                v[3 * u + 2] = ok ? xyz[3 * jj + 2] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                sx[j + 64 * u] = v[3 * u]; sy[j + 64 * u] = v[3 * u + 1]; sz[j + 64 * u] = v[3 * u + 2];
+            }
+        }
+        for (; j + 3 * 64 < np; j += 4 * 64) {    // then four
             float v[12];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -443,8 +458,11 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
             wave_max2(d0, d1, g0, g1);
             const uint32_t i0 = (uint32_t)(64 * blo) + (uint32_t)__builtin_ctzll(ballot(d0 == g0));
             const uint32_t i1 = (uint32_t)(64 * blo + 64) + (uint32_t)__builtin_ctzll(ballot(d1 == g1));
-            take_better(g0, i0, g_best, i_best);
-            take_better(g1, i1, g_best, i_best);
+            // Block blo precedes block blo+1, so between the two a tie keeps
+            // the first; only the merge with the out-of-window best needs
+            // the index comparison.
+            const bool later = g1 > g0;
+            take_better(later ? g1 : g0, later ? i1 : i0, g_best, i_best);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int blk = 64 * r + lane;
