@@ -256,9 +256,11 @@ int launch_grid_fps(const float* xyz, int32_t n, int32_t c, int32_t start, int32
         return fail(AFPS_ERR_UNSUPPORTED, "cloud of " + std::to_string(n) +
                                               " points exceeds the multi-workgroup FPS capacity");
     // Balance the blocks (the last one is not nearly empty); recount so that
-    // every workgroup owns at least one point.
+    // every workgroup owns at least one point.  Block indices travel in 16
+    // bits of the barrier word, so a block holds at most 65536 points.
     const int32_t chunk = (int32_t)(((int64_t)n + groups - 1) / groups);
     groups = (int)(((int64_t)n + chunk - 1) / chunk);
+    if (chunk > 65536) return fail(AFPS_ERR_UNSUPPORTED, "grid block too large");
     DeviceState* d;
     int rc = device_state(&d);
     if (rc) return rc;

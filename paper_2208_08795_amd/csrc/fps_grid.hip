@@ -2,29 +2,38 @@
 //
 // G workgroups (launched cooperatively, so all are resident) each keep a
 // contiguous block of `chunk` points in registers.  Every iteration each
-// workgroup updates its block and finds its lowest-index maximum, publishes
-// it in a per-workgroup slot, and arrives at a grid barrier (a release add on
-// one counter; the waiters spin with acquire loads).  After the barrier every
-// workgroup reads all G slots and takes the maximum, ties to the lowest
-// index: every workgroup reaches the same pick without a second barrier.
-// Slots are double-buffered by iteration parity: a workgroup can only
-// overwrite a parity-p slot after everybody passed the next barrier, i.e.
-// after everybody read it.  This per-iteration synchronisation is the cost
-// that the paper's sectors avoid (Sec. III-B).
+// workgroup updates its block and finds its lowest-index maximum, then
+// publishes it as ONE 64-bit word in its slot:
+//
+//     bits 63..32  distance (fp32 bits)
+//     bits 31..16  iteration tag (i mod 2^16)
+//     bits 15..0   index inside the workgroup's block (chunk <= 2^16)
+//
+// with a relaxed device-scope atomic store.  Every wave then polls all G
+// slots with relaxed device-scope atomic loads until each carries this
+// iteration's tag: the poll that completes the barrier also delivers every
+// candidate, and since each slot is a single atomic word no other memory
+// ordering is needed.  The winner is the maximum distance, ties to the lowest
+// workgroup (blocks are in index order) and within it the reported lowest
+// index; its coordinates are read from the (read-only) input.  Slots are
+// double-buffered by iteration parity: a workgroup can only overwrite a
+// parity-p slot after every workgroup published the next iteration, i.e.
+// after every workgroup read the parity-p slots.
 //
 // Every wait is bounded: after `spin_limit` polls a workgroup marks the
-// launch failed, returns, and the others notice the mark and return too;
-// workgroup 0 then fills the unfinished outputs with -1.
+// launch failed and returns, and the others notice the mark and return too;
+// workgroup 0 then fills the unfinished outputs with -1.  This per-iteration
+// synchronisation is the cost the paper's sectors avoid (Sec. III-B).
 #include "sampler.hpp"
 #include "variants.hpp"
 
 namespace afps {
 
 struct GridSync {
-    unsigned arrive;        // barrier arrivals since the reset
     unsigned failed;        // set when a workgroup gave up waiting
-    unsigned pad[62];
-    Candidate cand[2][kMaxGridGroups];
+    unsigned pad[63];
+    uint64_t slot[2][kMaxGridGroups];
+    uint64_t spare[(kGridSyncBytes - 256) / 8 - 2 * kMaxGridGroups];
 };
 static_assert(sizeof(GridSync) == kGridSyncBytes, "barrier block layout");
 
@@ -35,7 +44,6 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
                                                           unsigned spin_limit) {
     constexpr int T = 64 * W;
     __shared__ Candidate lds[2 * W];
-    __shared__ unsigned go;
     const int G = gridDim.x;
     const int g = blockIdx.x;
     const int t = threadIdx.x;
@@ -57,53 +65,42 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
     for (int i = 1; i < c; ++i) {
         const Pick mine = update_and_pick<P, T, false>(ns, w, lane, X, Y, Z, D, px, py, pz);
         const Pick p = combine_waves<W>(mine, lds, i & 1, w, lane);
-        if (t == 0) {
-            Candidate* slot = &gs->cand[i & 1][g];
-            slot->d = p.d;
-            slot->idx = (uint32_t)first + p.idx;
-            slot->x = p.x; slot->y = p.y; slot->z = p.z;
-            __hip_atomic_fetch_add(&gs->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned target = (unsigned)G * (unsigned)i;
-            unsigned ok = 1, spins = 0;
-            while (__hip_atomic_load(&gs->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins >= spin_limit ||
-                    ((spins & 255u) == 0 &&
-                     __hip_atomic_load(&gs->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                    ok = 0;
-                    break;
-                }
+        const uint64_t tag = (uint64_t)(i & 0xFFFF);
+        uint64_t* slots = gs->slot[i & 1];
+        if (t == 0)
+            __hip_atomic_store(&slots[g], ((uint64_t)p.d << 32) | (tag << 16) | (uint64_t)p.idx,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Poll every slot (lane l reads workgroup l's) until all carry tag i.
+        uint64_t v = 0;
+        bool ok = true;
+        for (unsigned spins = 0;; ++spins) {
+            if (lane < G) v = __hip_atomic_load(&slots[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool ready = lane >= G || ((v >> 16) & 0xFFFF) == tag;
+            if (ballot(!ready) == 0) break;
+            if (spins >= spin_limit ||
+                ((spins & 255u) == 255u &&
+                 __hip_atomic_load(&gs->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                ok = false;
+                break;
             }
-            if (!ok) __hip_atomic_store(&gs->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            go = ok;
+            __builtin_amdgcn_s_sleep(1);
         }
-        __syncthreads();
-        if (!go) {
-            if (g == 0) {
+        if (!ok) {
+            if (lane == 0) __hip_atomic_store(&gs->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (g == 0 && w == 0) {
                 const int done = i & ~63;   // picks before `done` are written
-                if (w == 0 && lane < (i & 63)) out[done + lane] = (int32_t)picks;
-                for (int j = i + t; j < c; j += T) out[j] = -1;
+                if (lane < (i & 63)) out[done + lane] = (int32_t)picks;
+                for (int j = i + lane; j < c; j += 64) out[j] = -1;
             }
-            return;
+            return;   // the wave's own exit; waves that still wait leave through their own polls
         }
-        // Acquire in every wave before reading the other workgroups' slots.
-        (void)__hip_atomic_load(&gs->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t ld = 0, li = 0xFFFFFFFFu;
-        float lx = 0.f, ly = 0.f, lz = 0.f;
-        if (lane < G) {
-            const Candidate* e = &gs->cand[i & 1][lane];
-            ld = e->d; li = e->idx; lx = e->x; ly = e->y; lz = e->z;
-        }
-        const uint32_t best = wave_max(ld);
-        const uint64_t tie = __ballot(lane < G && ld == best);
-        int win = (int)__builtin_ctzll(tie);
-        if (tie & (tie - 1)) {
-            const uint32_t key = ((tie >> lane) & 1) ? li : 0xFFFFFFFFu;
-            const uint32_t lowest = wave_min(key);
-            win = (int)__builtin_ctzll(__ballot(key == lowest));
-        }
-        const int cur = (int)readlane(li, win);
-        px = readlane(lx, win); py = readlane(ly, win); pz = readlane(lz, win);
+        const uint32_t d = lane < G ? (uint32_t)(v >> 32) : 0u;
+        const uint32_t best = wave_max(d);
+        const int win = (int)__builtin_ctzll(ballot(lane < G && d == best));
+        const int cur = win * chunk + (int)(readlane((uint32_t)(v & 0xFFFF), win));
+        px = xyz[3 * (int64_t)cur + 0];
+        py = xyz[3 * (int64_t)cur + 1];
+        pz = xyz[3 * (int64_t)cur + 2];
         const int slot = i & 63;
         picks = lane == slot ? (uint32_t)cur : picks;
         if (slot == 63 && g == 0 && w == 0) out[i - 63 + lane] = (int32_t)picks;
@@ -113,7 +110,12 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
 }
 
 __global__ void grid_reset(GridSync* gs) {
-    if (threadIdx.x == 0) { gs->arrive = 0u; gs->failed = 0u; }
+    const int t = threadIdx.x;
+    if (t == 0) gs->failed = 0u;
+    if (t < kMaxGridGroups) {
+        gs->slot[0][t] = 0ull;
+        gs->slot[1][t] = 0ull;
+    }
 }
 
 const void* grid_reset_kernel() { return (const void*)&grid_reset; }
