@@ -50,6 +50,7 @@ struct Registry {
     std::vector<VariantEntry> full;   // full-update sector kernels
     std::vector<NpduEntry> npdu;      // NPDU sector kernels, ascending capacity
     std::vector<GridVariant> grid;    // multi-workgroup plain FPS
+    std::vector<PoolEntry> pool;      // pooled NPDU kernel of batch plans, by waves
     Registry() {
         register_variants_w1(full);
         register_variants_w2(full);
@@ -58,6 +59,7 @@ struct Registry {
         register_variants_w16(full);
         register_npdu_variants(npdu);
         register_grid_variants(grid);
+        register_pool_variants(pool);
     }
 };
 
@@ -150,6 +152,7 @@ struct DeviceState {
     bool ready = false;
     int cu_count = 0;
     size_t max_lds = 0;
+    int pool_pages = 0;                      // LDS pages of one pooled-NPDU workgroup
     std::vector<hipStream_t> helpers;        // bucket streams for batch plans
     void* grid_pool = nullptr;               // grid-barrier blocks
     std::vector<hipEvent_t> grid_events;     // last user of each block
@@ -173,6 +176,12 @@ int device_state(DeviceState** out) {
         AFPS_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         d.cu_count = cus;
         d.max_lds = (size_t)lds;
+        // The pool takes a CU's whole LDS, less the kernel's static header.
+        int per_cu = 0;
+        if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            per_cu <= 0)
+            per_cu = lds;
+        d.pool_pages = std::min(kMaxPoolPages, (per_cu - 256) / kPoolPageBytes);
         // Kernels that take more than the default dynamic LDS.
         for (const auto& v : registry().full)
             if (v.lds_bytes > 0) {
@@ -182,8 +191,10 @@ int device_state(DeviceState** out) {
         for (const auto& v : registry().npdu) {
             const int b = npdu_lds_bytes(v, capacity(v));
             (void)hipFuncSetAttribute(v.direct, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-            (void)hipFuncSetAttribute(v.persistent, hipFuncAttributeMaxDynamicSharedMemorySize, b);
         }
+        for (const auto& v : registry().pool)
+            (void)hipFuncSetAttribute(v.kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      d.pool_pages * kPoolPageBytes);
         (void)hipGetLastError();
         d.ready = true;
     }
@@ -448,17 +459,29 @@ struct Bucket {
     int grid;             // workgroups launched
     double cost;          // estimated work (cycles of one workgroup), for ordering and sizing
     double longest;       // estimated cycles of the bucket's longest item
+    bool pool;            // the pooled NPDU kernel (queues below, not one counter)
 };
 
-
-constexpr size_t kCounterBytes = 256;   // queue counters, one per bucket
+// Workspace of a plan: [bucket counters | pool queue counters | pool queue
+// table | work items].
+constexpr size_t kCounterBytes = 256;                                   // one per bucket
 constexpr int kMaxBuckets = (int)(kCounterBytes / sizeof(unsigned));
+constexpr size_t kPoolCounterOffset = kCounterBytes;                    // one per pool queue
+constexpr size_t kPoolTableOffset = kPoolCounterOffset + kMaxPoolQueues * sizeof(unsigned);
+constexpr size_t kItemsOffset = kPoolTableOffset + kMaxPoolQueues * sizeof(PoolQueue);
+static_assert(kItemsOffset % 256 == 0, "work items start 256-byte aligned");
+constexpr int kResetWords = (int)(kPoolTableOffset / sizeof(unsigned));
+
+// Estimated cycles of one NPDU iteration (one wave, window of two blocks).
+constexpr double kNpduIterCycles = 650.0;
 
 }  // namespace
 
 struct afps_plan {
     std::vector<WorkItem> items;
     std::vector<Bucket> buckets;
+    std::vector<PoolQueue> queues;    // pool queues, highest priority first
+    int pool_pages = 0;
     size_t ws_bytes = 0;
     int device = 0;
     std::vector<hipEvent_t> events;   // fork / join events (1 + helper streams)
@@ -485,8 +508,9 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
 
     struct Staged {
         WorkItem item;
-        const void* kernel;
-        int block, lds;   // lds: the bucket's dynamic LDS (size class of the sector)
+        const void* kernel;   // full-update variant; nullptr = NPDU (pooled)
+        int block, lds;       // full-update: workgroup size and dynamic LDS
+        int pages;            // NPDU: pool pages
         double cost;
     };
     std::vector<Staged> staged;
@@ -499,7 +523,7 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         if (rc) return fail(rc, where + g_last_error);
         const int32_t qn = d.n / d.m, rn = d.n % d.m, qc = d.c / d.m, rc_ = d.c % d.m;
         for (int32_t s = 0; s < d.m; ++s) {
-            Staged st;
+            Staged st{};
             WorkItem& it = st.item;
             const int32_t ns = qn + (s < rn ? 1 : 0), bs = s * qn + std::min(s, rn);
             const int32_t cs = qc + (s < rc_ ? 1 : 0), os = s * qc + std::min(s, rc_);
@@ -512,16 +536,12 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             it.base = bs;
             it.pad = 0;
             if (d.k >= 0) {
-                const NpduEntry* v = choose_npdu(ns);
-                if (!v) return fail(AFPS_ERR_UNSUPPORTED, where + "NPDU sector too large");
-                st.kernel = v->persistent;
-                st.block = 64;
-                st.cost = (double)cs * 950.0;   // cycles per NPDU iteration, nearly independent of n_s
-                // LDS size classes (sectors of <= 512, 1024, 2048, 4096... points):
-                // small sectors keep many workgroups resident per CU.
-                int cls = 512;
-                while (cls < ns) cls *= 2;
-                st.lds = npdu_lds_bytes(*v, std::min(cls, capacity(*v)));
+                if (npdu_r_for(ns) == 0) return fail(AFPS_ERR_UNSUPPORTED, where + "NPDU sector too large");
+                st.kernel = nullptr;
+                st.pages = npdu_pool_pages(ns);
+                // iterations of the window update; sectors whose window spans
+                // more than two blocks re-reduce one more block per extra 64
+                st.cost = (double)cs * kNpduIterCycles * (1.0 + std::max(0, it.k - 64) / 128.0);
             } else {
                 const VariantEntry* v = ns <= kMaxFullSector ? choose_full(ns, true) : nullptr;
                 if (!v)
@@ -540,18 +560,84 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             staged.push_back(st);
         }
     }
-    // Group by kernel; inside a group, longest first.
-    // Group by (kernel, LDS class); inside a group, longest first.
-    std::stable_sort(staged.begin(), staged.end(), [](const Staged& a, const Staged& b) {
+    DeviceState* ds = nullptr;
+    if (!staged.empty()) {
+        int rc = device_state(&ds);
+        if (rc) return rc;
+        AFPS_HIP(hipGetDevice(&plan->device));
+        plan->pool_pages = ds->pool_pages;
+    }
+
+    // NPDU sectors: one pool bucket.  Queues by page count, each longest
+    // first; queues ordered by their longest sector.
+    std::vector<Staged> npdu, full;
+    for (auto& st : staged) (st.kernel ? full : npdu).push_back(st);
+    std::stable_sort(npdu.begin(), npdu.end(), [](const Staged& a, const Staged& b) {
+        if (a.pages != b.pages) return a.pages > b.pages;
+        return a.cost > b.cost;
+    });
+    std::vector<std::pair<double, std::pair<int, int>>> qorder;   // (longest cost, [first, count))
+    for (size_t i = 0; i < npdu.size();) {
+        size_t j = i;
+        while (j < npdu.size() && npdu[j].pages == npdu[i].pages) ++j;
+        if (npdu[i].pages > plan->pool_pages)
+            return fail(AFPS_ERR_UNSUPPORTED, "NPDU sector of " + std::to_string(npdu[i].item.n) +
+                                                  " points exceeds the LDS of one CU");
+        qorder.push_back({npdu[i].cost, {(int)i, (int)(j - i)}});
+        i = j;
+    }
+    if ((int)qorder.size() > kMaxPoolQueues) return fail(AFPS_ERR_UNSUPPORTED, "too many NPDU sector sizes");
+    std::stable_sort(qorder.begin(), qorder.end(),
+                     [](const auto& a, const auto& b) { return a.first > b.first; });
+
+    // Full-update sectors: one bucket per (kernel, LDS), longest first inside.
+    std::stable_sort(full.begin(), full.end(), [](const Staged& a, const Staged& b) {
         if (a.kernel != b.kernel) return a.kernel < b.kernel;
         if (a.lds != b.lds) return a.lds < b.lds;
         return a.cost > b.cost;
     });
-    for (size_t i = 0; i < staged.size();) {
+
+    plan->items.reserve(staged.size());
+    if (!npdu.empty()) {
+        Bucket bk{nullptr, 0, 0, 0, 0, 0, 0.0, 0.0, true};
+        for (const auto& q : qorder) {
+            const int first = (int)plan->items.size();
+            for (int i = 0; i < q.second.second; ++i) {
+                const Staged& st = npdu[q.second.first + i];
+                plan->items.push_back(st.item);
+                bk.cost += st.cost;
+                bk.longest = std::max(bk.longest, st.cost);
+            }
+            plan->queues.push_back({first, q.second.second, npdu[q.second.first].pages, 0});
+        }
+        bk.count = (int)plan->items.size();
+        // Waves per CU: one per SIMD keeps the longest sectors at full speed;
+        // two per SIMD give more throughput (about 1.7x) when the batch is
+        // bound by total work rather than by its longest sector.
+        const double cus = (double)ds->cu_count;
+        const double span4 = std::max(bk.longest, bk.cost / (4.0 * cus));
+        const double span8 = std::max(1.18 * bk.longest, bk.cost / (6.8 * cus));
+        int waves = span8 < span4 ? 8 : 4;
+        if (g_waves_per_simd > 0.0f) waves = g_waves_per_simd < 1.5f ? 4 : 8;
+        const PoolEntry* pe = nullptr;
+        for (const auto& v : registry().pool)
+            if (v.waves == waves) pe = &v;
+        if (!pe) return fail(AFPS_ERR_UNSUPPORTED, "pooled NPDU kernel missing");
+        bk.kernel = pe->kernel;
+        bk.block = 64 * pe->waves;
+        bk.lds_bytes = plan->pool_pages * kPoolPageBytes;
+        bk.grid = std::min(ds->cu_count, bk.count);
+        plan->buckets.push_back(bk);
+    }
+    std::vector<double> item_cost(plan->items.size(), 0.0);   // estimated cycles, aligned with items
+    for (size_t i = 0; i < full.size();) {
         size_t j = i;
-        Bucket bk{staged[i].kernel, staged[i].block, staged[i].lds, (int)i, 0, 0, 0.0, staged[i].cost};
-        while (j < staged.size() && staged[j].kernel == bk.kernel && staged[j].lds == bk.lds_bytes) {
-            bk.cost += staged[j].cost;
+        Bucket bk{full[i].kernel, full[i].block, full[i].lds, (int)plan->items.size(), 0, 0, 0.0, 0.0, false};
+        while (j < full.size() && full[j].kernel == bk.kernel && full[j].lds == bk.lds_bytes) {
+            bk.cost += full[j].cost;
+            bk.longest = std::max(bk.longest, full[j].cost);
+            plan->items.push_back(full[j].item);
+            item_cost.push_back(full[j].cost);
             ++j;
         }
         bk.count = (int)(j - i);
@@ -560,29 +646,12 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     }
     if ((int)plan->buckets.size() > kMaxBuckets) return fail(AFPS_ERR_UNSUPPORTED, "too many kernel variants in one plan");
     // Largest bucket first: it gets the first helper stream.
-    std::sort(plan->buckets.begin(), plan->buckets.end(),
-              [](const Bucket& a, const Bucket& b) { return a.cost > b.cost; });
-    plan->items.reserve(staged.size());
-    std::vector<double> item_cost(staged.size());   // estimated cycles, aligned with items
-    {
-        std::vector<WorkItem> ordered(staged.size());
-        int pos = 0;
-        for (auto& bk : plan->buckets) {
-            for (int i = 0; i < bk.count; ++i) {
-                ordered[pos + i] = staged[bk.first + i].item;
-                item_cost[pos + i] = staged[bk.first + i].cost;
-            }
-            bk.first = pos;
-            pos += bk.count;
-        }
-        plan->items.swap(ordered);
-    }
-    // Persistent grid: as many workgroups as stay resident, at most one per item.
+    std::stable_sort(plan->buckets.begin(), plan->buckets.end(),
+                     [](const Bucket& a, const Bucket& b) { return a.cost > b.cost; });
+
+    // Full-update persistent grids: as many workgroups as stay resident, at
+    // most one per item.
     if (!plan->buckets.empty()) {
-        DeviceState* ds;
-        int rc = device_state(&ds);
-        if (rc) return rc;
-        AFPS_HIP(hipGetDevice(&plan->device));
         // Makespan model: the queue hands out items longest first, so a
         // bucket run by g workgroups finishes when the longest-processing-
         // time (LPT) schedule of its item costs on g machines does.  Take
@@ -596,11 +665,12 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         double T = 0.0;
         for (size_t b = 0; b < plan->buckets.size(); ++b) {
             Bucket& bk = plan->buckets[b];
+            T = std::max(T, bk.longest);
+            if (bk.pool) continue;
             int per_cu = 0;
             AFPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bk.kernel, bk.block, bk.lds_bytes));
             if (per_cu < 1) return fail(AFPS_ERR_UNSUPPORTED, "a kernel variant cannot be resident");
             cap[b] = std::min(bk.count, per_cu * ds->cu_count);
-            T = std::max(T, bk.longest);
         }
         auto lpt_makespan = [&](const Bucket& bk, int g) {
             std::vector<double> load(g, 0.0);   // min-heap of machine loads
@@ -626,13 +696,14 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             return hi;
         };
         if (g_waves_per_simd <= 0.0f) {
-            for (size_t b = 0; b < plan->buckets.size(); ++b) plan->buckets[b].grid = cap[b];
+            for (size_t b = 0; b < plan->buckets.size(); ++b)
+                if (!plan->buckets[b].pool) plan->buckets[b].grid = cap[b];
         } else {
             for (int round = 0; round < 200; ++round) {
                 double waves = 0.0;
                 for (size_t b = 0; b < plan->buckets.size(); ++b) {
                     Bucket& bk = plan->buckets[b];
-                    bk.grid = workgroups_for(b, T);
+                    if (!bk.pool) bk.grid = workgroups_for(b, T);
                     waves += (double)bk.grid * (bk.block / 64);
                 }
                 if (waves <= budget) break;
@@ -659,10 +730,11 @@ size_t afps_plan_workspace_bytes(const afps_plan* plan) { return plan ? plan->ws
 
 size_t afps_workspace_bytes_for_items(int32_t items) {
     if (items <= 0) return 0;
-    const size_t b = kCounterBytes + (size_t)items * sizeof(WorkItem);
+    const size_t b = kItemsOffset + (size_t)items * sizeof(WorkItem);
     return (b + 255) / 256 * 256;
 }
 int32_t afps_plan_items(const afps_plan* plan) { return plan ? (int32_t)plan->items.size() : 0; }
+
 int32_t afps_plan_launches(const afps_plan* plan) { return plan ? (int32_t)plan->buckets.size() : 0; }
 
 void afps_plan_destroy(afps_plan* plan) { delete plan; }
@@ -673,8 +745,12 @@ int afps_plan_upload(afps_plan* plan, void* workspace, size_t workspace_bytes, v
     if (!workspace || workspace_bytes < plan->ws_bytes)
         return fail(AFPS_ERR_WORKSPACE, "workspace needs " + std::to_string(plan->ws_bytes) + " bytes");
     if (((uintptr_t)workspace & 255) != 0) return fail(AFPS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    // Pageable source: the copy has consumed the host table when this returns.
-    AFPS_HIP(hipMemcpyAsync((char*)workspace + kCounterBytes, plan->items.data(),
+    // Pageable sources: the copies have consumed the host tables when this returns.
+    if (!plan->queues.empty())
+        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolTableOffset, plan->queues.data(),
+                                plan->queues.size() * sizeof(PoolQueue), hipMemcpyHostToDevice,
+                                (hipStream_t)stream));
+    AFPS_HIP(hipMemcpyAsync((char*)workspace + kItemsOffset, plan->items.data(),
                             plan->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
                             (hipStream_t)stream));
     return AFPS_OK;
@@ -688,13 +764,25 @@ int afps_plan_launch(const afps_plan* plan, const float* xyz_all, int32_t* out_a
     if (!workspace) return fail(AFPS_ERR_WORKSPACE, "workspace must be non-null");
     hipStream_t stream = (hipStream_t)stream_;
     unsigned* counters = (unsigned*)workspace;
-    const WorkItem* items = (const WorkItem*)((char*)workspace + kCounterBytes);
+    unsigned* qtaken = (unsigned*)((char*)workspace + kPoolCounterOffset);
+    const PoolQueue* queues = (const PoolQueue*)((char*)workspace + kPoolTableOffset);
+    const WorkItem* items = (const WorkItem*)((char*)workspace + kItemsOffset);
     int nb = (int)plan->buckets.size();
-    void* rargs[] = {&counters, &nb};
-    AFPS_HIP(hipLaunchKernel(queue_reset_kernel(), dim3(1), dim3(64), rargs, 0, stream));
+    int reset_words = kResetWords;
+    void* rargs[] = {&counters, &reset_words};
+    AFPS_HIP(hipLaunchKernel(queue_reset_kernel(), dim3(1), dim3(kResetWords), rargs, 0, stream));
 
     auto launch_bucket = [&](int b, hipStream_t s) -> int {
         const Bucket& bk = plan->buckets[b];
+        if (bk.pool) {
+            int nq = (int)plan->queues.size();
+            int pages = plan->pool_pages;
+            unsigned spin = g_spin_limit;
+            void* args[] = {(void*)&xyz_all, (void*)&out_all, (void*)&items, (void*)&queues,
+                            &nq, (void*)&qtaken, &pages, &spin};
+            AFPS_HIP(hipLaunchKernel(bk.kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
+            return AFPS_OK;
+        }
         const WorkItem* first = items + bk.first;
         int count = bk.count;
         unsigned* counter = counters + b;

@@ -1,0 +1,204 @@
+// Pooled NPDU kernel (Sec. III-C sectors of a whole batch in one launch).
+//
+// One workgroup per CU takes the CU's whole LDS as a pool of 1 KB pages (64
+// sector records of 16 bytes).  Its W waves work independently: a wave
+// allocates exactly the pages of one sector (first fit, contiguous), samples
+// it with the one-wave NPDU sampler, frees the pages and takes the next
+// sector.  Sectors wait in priority queues, one per page count, ordered by
+// their longest sector first; a wave takes the first queue whose sectors fit
+// in the largest free run of its pool, so the long sectors (the critical path
+// of the batch) start first and the short ones fill the pages left over.
+//
+// Allocation is serialised per workgroup by an LDS lock; frees are atomic
+// ANDs on the used-mask and need no lock.  Every wait (for the lock, or for
+// pages another wave of the workgroup still holds) polls at most spin_limit
+// times; a wave that gives up marks every sector still queued as failed
+// (outputs -1) so that no output is left unwritten, and exits.
+#include "sampler.hpp"
+#include "variants.hpp"
+
+namespace afps {
+
+namespace {
+
+// Number of consecutive 1 bits of x from bit 0.
+__device__ __forceinline__ int ones_from_bottom(uint64_t x) {
+    return ~x == 0ull ? 64 : (int)__builtin_ctzll(~x);
+}
+// Free pages from page 64*w + lane onwards, for the three words of the
+// used-mask u (bit set = page in use); pages past the pool are marked used.
+__device__ __forceinline__ int free_run(int w, int lane, uint64_t u0, uint64_t u1, uint64_t u2) {
+    const uint64_t uw = w == 0 ? u0 : (w == 1 ? u1 : u2);
+    int run = ones_from_bottom(~uw >> lane);
+    if (run < 64 - lane) return run;        // a used page inside this word ends the run
+    run = 64 - lane;
+    if (w < 1) {
+        const int r1 = ones_from_bottom(~u1);
+        run += r1;
+        if (r1 < 64) return run;
+    }
+    if (w < 2) run += ones_from_bottom(~u2);
+    return run;
+}
+// Bits of pages [s, s + p) inside word w of the used-mask.
+__device__ __forceinline__ uint64_t page_bits(int w, int s, int p) {
+    const int lo = max(s, 64 * w), hi = min(s + p, 64 * w + 64);
+    if (lo >= hi) return 0ull;
+    const int len = hi - lo;
+    const uint64_t ones = len == 64 ? ~0ull : ((1ull << len) - 1ull);
+    return ones << (lo - 64 * w);
+}
+
+__device__ __forceinline__ void fail_item(const WorkItem& wi, int32_t* out_all, int lane) {
+    int32_t* out = out_all + wi.out_offset;
+    for (int j = lane; j < wi.c; j += 64) out[j] = -1;
+}
+
+// Sample one sector with the NPDU variant its size calls for; `lds` is the
+// first of its pages.
+__device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int32_t* __restrict__ out_all,
+                                         const WorkItem& wi, uint32_t* lds) {
+    const float* xyz = xyz_all + 3 * wi.xyz_offset;
+    int32_t* out = out_all + wi.out_offset;
+    switch (npdu_r_for(wi.n)) {
+        case 1: sample_sector_npdu<1, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
+        case 2: sample_sector_npdu<2, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
+        case 4: sample_sector_npdu<4, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
+        default: sample_sector_npdu<8, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
+    }
+}
+
+}  // namespace
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __restrict__ xyz_all,
+                                                             int32_t* __restrict__ out_all,
+                                                             const WorkItem* __restrict__ items,
+                                                             const PoolQueue* __restrict__ queues,
+                                                             int nq, unsigned* qtaken, int pool_pages,
+                                                             unsigned spin_limit) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t pool[];
+    __shared__ uint64_t used[3];
+    __shared__ uint32_t lock;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 3) {
+        const int lo = 64 * (int)threadIdx.x;
+        used[threadIdx.x] = pool_pages <= lo ? ~0ull : (pool_pages >= lo + 64 ? 0ull : (~0ull << (pool_pages - lo)));
+    }
+    if (threadIdx.x == 0) lock = 0u;
+    __syncthreads();   // the only workgroup barrier: from here on waves are independent
+
+    // This lane's two queues (lane, lane + 64): their page counts and sizes.
+    const int q0 = lane, q1 = lane + 64;
+    const int pages0 = q0 < nq ? queues[q0].pages : 0x7FFFFFFF, count0 = q0 < nq ? queues[q0].count : 0;
+    const int pages1 = q1 < nq ? queues[q1].pages : 0x7FFFFFFF, count1 = q1 < nq ? queues[q1].count : 0;
+
+    unsigned spins = 0;
+    bool failed = false;
+    for (;;) {
+        // ---- take the allocation lock (lane 0 polls; the wave follows)
+        int got = 0;
+        if (lane == 0) {
+            for (;;) {
+                uint32_t expected = 0u;
+                if (__hip_atomic_compare_exchange_strong(&lock, &expected, 1u, __ATOMIC_ACQUIRE,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    got = 1;
+                    break;
+                }
+                if (++spins >= spin_limit) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        spins = (unsigned)__builtin_amdgcn_readfirstlane((int)spins);
+        if (!__builtin_amdgcn_readfirstlane(got)) {
+            failed = true;
+            break;
+        }
+
+        // ---- largest free run of pages, per start page (three per lane)
+        const uint64_t u0 = __hip_atomic_load(&used[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint64_t u1 = __hip_atomic_load(&used[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint64_t u2 = __hip_atomic_load(&used[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int r0 = free_run(0, lane, u0, u1, u2);
+        const int r1 = free_run(1, lane, u0, u1, u2);
+        const int r2 = free_run(2, lane, u0, u1, u2);
+        const int longest = (int)wave_max((uint32_t)max(r0, max(r1, r2)));
+
+        // ---- first queue (highest priority) with sectors left that fit
+        const unsigned t0 = q0 < nq ? __hip_atomic_load(&qtaken[q0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const unsigned t1 = q1 < nq ? __hip_atomic_load(&qtaken[q1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        const bool left0 = t0 < (unsigned)count0, left1 = t1 < (unsigned)count1;
+        if ((ballot(left0) | ballot(left1)) == 0ull) {           // every queue is drained
+            if (lane == 0) __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            break;
+        }
+        const uint64_t fit0 = ballot(left0 && pages0 <= longest), fit1 = ballot(left1 && pages1 <= longest);
+        int q = -1;
+        if (fit0) q = (int)__builtin_ctzll(fit0);
+        else if (fit1) q = 64 + (int)__builtin_ctzll(fit1);
+        int item = -1;
+        if (q >= 0) {
+            unsigned idx = 0;
+            if (lane == 0) idx = atomicAdd(&qtaken[q], 1u);
+            idx = (unsigned)__builtin_amdgcn_readfirstlane((int)idx);
+            const PoolQueue Q = queues[q];
+            if (idx < (unsigned)Q.count) item = Q.first + (int)idx;
+        }
+        if (item < 0) {
+            // Nothing fits now (pages held by other waves of this workgroup),
+            // or the queue emptied meanwhile: release and poll again.
+            if (lane == 0) __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (q < 0) {
+                if (++spins >= spin_limit) {
+                    failed = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            continue;
+        }
+
+        // ---- first fit of the item's pages, marked used, lock released
+        const int p = q < 64 ? __builtin_amdgcn_readlane(pages0, q) : __builtin_amdgcn_readlane(pages1, q - 64);
+        const uint64_t b0 = ballot(r0 >= p), b1 = ballot(r1 >= p), b2 = ballot(r2 >= p);
+        const int s = b0 ? (int)__builtin_ctzll(b0) : (b1 ? 64 + (int)__builtin_ctzll(b1) : 128 + (int)__builtin_ctzll(b2));
+        const uint64_t m0 = page_bits(0, s, p), m1 = page_bits(1, s, p), m2 = page_bits(2, s, p);
+        if (lane == 0) {
+            if (m0) __hip_atomic_fetch_or(&used[0], m0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (m1) __hip_atomic_fetch_or(&used[1], m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (m2) __hip_atomic_fetch_or(&used[2], m2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // the previous owner's accesses are done
+
+        const WorkItem wi = items[item];
+        run_item(xyz_all, out_all, wi, pool + s * (kPoolPageBytes / 4));
+
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // this sector's accesses are done
+        if (lane == 0) {
+            if (m0) __hip_atomic_fetch_and(&used[0], ~m0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (m1) __hip_atomic_fetch_and(&used[1], ~m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (m2) __hip_atomic_fetch_and(&used[2], ~m2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    if (!failed) return;
+    // Gave up waiting: take every sector still queued and mark it failed.
+    for (int q = 0; q < nq; ++q) {
+        const PoolQueue Q = queues[q];
+        for (;;) {
+            unsigned idx = 0;
+            if (lane == 0) idx = atomicAdd(&qtaken[q], 1u);
+            idx = (unsigned)__builtin_amdgcn_readfirstlane((int)idx);
+            if (idx >= (unsigned)Q.count) break;
+            fail_item(items[Q.first + (int)idx], out_all, lane);
+        }
+    }
+}
+
+void register_pool_variants(std::vector<PoolEntry>& v) {
+    v.push_back({4, (const void*)&pooled_npdu_kernel<4>});
+    v.push_back({8, (const void*)&pooled_npdu_kernel<8>});
+}
+
+}  // namespace afps

@@ -316,6 +316,136 @@ __device__ __forceinline__ void sample_sector(const float* __restrict__ xyz, int
     if (w == 0 && tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
 }
 
+// v_writelane_b32 (clang declares no builtin for it): `old` with lane `lane`
+// (wave-uniform) replaced by the wave-uniform `value`.
+extern "C" __device__ int afps_llvm_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane");
+__device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t value, int lane) {
+    return (uint32_t)afps_llvm_writelane((int)value, lane, (int)old);
+}
+
+// A sector of the NPDU samplers belongs to one wave: its LDS stores need only
+// have completed before its own later loads, with no workgroup barrier (other
+// waves of the workgroup may be sampling other sectors).
+__device__ __forceinline__ void sector_lds_ready() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+}
+
+// NPDU on one sector (Sec. III-C) for narrow windows, one wave:
+//   n <= 4096 (at most 64 blocks of 64 points: one block maximum per lane)
+//   k <= 64   (the window's at most k+1 points lie in two adjacent blocks)
+// Arguments as for sample_sector_npdu below; lds holds npdu_padded_points(n)
+// records of 16 bytes {D bits, x, y, z}, so a point is one 128-bit LDS read.
+//
+// Per iteration, in issue order (one wave issues one instruction at a time,
+// so the loop is written for few instructions):
+//   1. read the sample's record and the two blocks holding its window;
+//   2. while the reads are in flight, the maximum over the other blocks;
+//   3. update the window points of the two blocks, store their D;
+//   4. re-reduce both blocks (two interleaved DPP chains), write their maxima
+//      and first indices into their lanes;
+//   5. the overall maximum is the larger of (2) and (4); the lowest lane
+//      holding it is the lowest block, whose first index is the next sample.
+// Ties therefore go to the lowest index, as in Algorithm 1.
+__device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restrict__ xyz, int n, int c,
+                                                          int k, int cur, int base,
+                                                          int32_t* __restrict__ out, uint32_t* lds) {
+    const int lane = threadIdx.x & 63;
+    const int nb = (n + 63) >> 6;
+    const int np = npdu_padded_points(n);
+    uint32_t* rec = static_cast<uint32_t*>(__builtin_assume_aligned(lds, 16));
+    // Records are read as whole 16-byte copies (char-typed, so they are
+    // ordered with the 32-bit D stores of earlier iterations).
+    auto read = [rec](int j) {
+        uint4 r;
+        __builtin_memcpy(&r, rec + 4 * j, 16);
+        return r;
+    };
+    auto write = [rec](int j, uint32_t d, float x, float y, float z) {
+        const uint4 r = make_uint4(d, __float_as_uint(x), __float_as_uint(y), __float_as_uint(z));
+        __builtin_memcpy(rec + 4 * j, &r, 16);
+    };
+    const uint32_t init = __float_as_uint(kInitialDistance);
+
+    // Load: sixteen points in flight per lane; indices past n read point n-1
+    // and store a padding record (D = 0, never inside a window).
+    {
+        int j = lane;
+        for (; j + 15 * 64 < np; j += 16 * 64) {
+            float v[48];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int jj = min(j + 64 * u, n - 1);
+                v[3 * u] = xyz[3 * jj];
+                v[3 * u + 1] = xyz[3 * jj + 1];
+                v[3 * u + 2] = xyz[3 * jj + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int jj = j + 64 * u;
+                write(jj, jj < n ? init : 0u, v[3 * u], v[3 * u + 1], v[3 * u + 2]);
+            }
+        }
+        for (; j < np; j += 64) {
+            const int jj = min(j, n - 1);
+            write(j, j < n ? init : 0u, xyz[3 * jj], xyz[3 * jj + 1], xyz[3 * jj + 2]);
+        }
+    }
+    sector_lds_ready();
+
+    // Lanes past the last block hold 0: a lower lane holds a value >= 0, so
+    // they never win the lowest-lane search below.
+    uint32_t bm = lane < nb ? init : 0u;
+    uint32_t bi = (uint32_t)(64 * lane);
+    const int below = k >> 1, above = k - (k >> 1);
+    uint32_t picks = (uint32_t)(base + cur);   // pick i in lane i mod 64, written 64 at a time
+
+    for (int i = 1; i < c; ++i) {
+        const int lo = max(0, cur - below);
+        const int hi = min(n - 1, cur + above);
+        const int blo = lo >> 6;
+        const int j0 = 64 * blo + lane;
+        const uint4 P = read(cur);
+        const uint4 A = read(j0);
+        const uint4 B = read(j0 + 64);
+
+        const uint32_t g_out = wave_max((uint32_t)(lane - blo) > 1u ? bm : 0u);
+
+        // Window: point j0 is in it iff 0 <= t <= hi - lo, point j0 + 64 iff
+        // t + 64 <= hi - lo, with t = j0 - lo.
+        const int t = lane - (lo & 63);
+        const int span = hi - lo;
+        const float px = __uint_as_float(P.y), py = __uint_as_float(P.z), pz = __uint_as_float(P.w);
+        const uint32_t e0 = min(A.x, sq_dist_bits(__uint_as_float(A.y), __uint_as_float(A.z),
+                                                  __uint_as_float(A.w), px, py, pz));
+        const uint32_t e1 = min(B.x, sq_dist_bits(__uint_as_float(B.y), __uint_as_float(B.z),
+                                                  __uint_as_float(B.w), px, py, pz));
+        const uint32_t d0 = (uint32_t)t <= (uint32_t)span ? e0 : A.x;
+        const uint32_t d1 = t <= span - 64 ? e1 : B.x;
+        rec[4 * j0] = d0;
+        rec[4 * (j0 + 64)] = d1;
+
+        uint32_t g0, g1;
+        wave_max2(d0, d1, g0, g1);
+        const uint32_t i0 = (uint32_t)(64 * blo) + (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+        const uint32_t i1 = (uint32_t)(64 * blo + 64) + (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+        // Block blo+1 may be the padding block (g1 = 0) or, for n = 4096,
+        // lane 64, which does not exist: then it goes to lane 63 first and
+        // block blo = 63 overwrites it.
+        const int l1 = min(blo + 1, 63);
+        bm = writelane(bm, g1, l1);
+        bi = writelane(bi, i1, l1);
+        bm = writelane(bm, g0, blo);
+        bi = writelane(bi, i0, blo);
+
+        const uint32_t g = max(g_out, max(g0, g1));
+        cur = (int)readlane(bi, (int)__builtin_ctzll(ballot(bm == g)));
+        picks = writelane(picks, (uint32_t)(base + cur), i & 63);
+        if ((i & 63) == 63) out[i - 63 + lane] = (int32_t)picks;
+    }
+    const int tail = (c - 1) & 63;   // picks of the last, partial group
+    if (tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
+}
+
 // NPDU on one sector (Sec. III-C), one wave.
 //   xyz   : the sector's first point in global memory
 //   n, c  : points and samples (1 <= c <= n <= 4096*R)
@@ -339,6 +469,12 @@ template <int R, bool XYZ_IN_LDS>
 __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz, int n, int c,
                                                    int k, int cur, int base,
                                                    int32_t* __restrict__ out, uint32_t* lds) {
+    if constexpr (R == 1 && XYZ_IN_LDS) {
+        if (k <= 64) {
+            sample_sector_npdu_narrow(xyz, n, c, k, cur, base, out, lds);
+            return;
+        }
+    }
     const int lane = threadIdx.x & 63;
     const int nb = (n + 63) >> 6;                 // blocks holding points
     const int np = npdu_padded_points(n);
@@ -387,7 +523,7 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
         }
     }
     for (int j = lane; j < np; j += 64) sd[j] = j < n ? __float_as_uint(kInitialDistance) : 0u;
-    __syncthreads();
+    sector_lds_ready();
 
     uint32_t bm[R], bi[R];
 #pragma unroll

@@ -42,7 +42,6 @@ struct NpduEntry {
     int chunk64;            // R: a sector holds <= 64*64*R points
     int xyz_in_lds;         // 1: x,y,z and D in LDS (16 B/point); 0: only D (4 B/point)
     const void* direct;
-    const void* persistent;
 };
 void register_npdu_variants(std::vector<NpduEntry>& v);
 
@@ -51,6 +50,36 @@ void register_npdu_variants(std::vector<NpduEntry>& v);
 __host__ __device__ constexpr int npdu_padded_points(int n) { return ((n + 63) / 64 + 1) * 64; }
 __host__ __device__ constexpr int npdu_lds_words(int n, bool xyz_in_lds) {
     return (xyz_in_lds ? 4 : 1) * npdu_padded_points(n);
+}
+
+// Pooled NPDU kernel (kernels_pool.hip): one workgroup per CU owns the CU's
+// LDS as pages of 1 KB (64 records of 16 bytes); each of its W waves takes
+// sectors from priority queues and holds exactly the pages its sector needs.
+struct PoolQueue {
+    int32_t first;     // items [first, first + count) of the plan, longest first
+    int32_t count;
+    int32_t pages;     // pages every item of the queue needs
+    int32_t pad;
+};
+static_assert(sizeof(PoolQueue) == 16, "pool queue layout");
+constexpr int kPoolPageBytes = 1024;
+constexpr int kMaxPoolPages = 160;      // pages per workgroup, at most (used-mask of 3 words)
+constexpr int kMaxPoolQueues = 128;     // two per lane in the queue scan
+struct PoolEntry {
+    int waves;
+    const void* kernel;
+};
+void register_pool_variants(std::vector<PoolEntry>& v);
+
+// Blocks of 64 points per lane register (R) of the NPDU kernel holding a
+// sector of n points, and whether x, y, z live in LDS (R <= 2) or are read
+// from global memory (R >= 4); 0 if n is too large.
+__host__ __device__ constexpr int npdu_r_for(int n) {
+    return n <= 4096 ? 1 : n <= 8192 ? 2 : n <= 16384 ? 4 : n <= 32768 ? 8 : 0;
+}
+// Pages of the pool a sector of n points occupies.
+__host__ __device__ constexpr int npdu_pool_pages(int n) {
+    return (4 * npdu_lds_words(n, npdu_r_for(n) <= 2) + kPoolPageBytes - 1) / kPoolPageBytes;
 }
 
 // Multi-workgroup plain FPS (fps_grid.hip).

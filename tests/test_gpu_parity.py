@@ -130,6 +130,28 @@ def test_every_npdu_variant_agrees(B, torch_dev, q):
         _check(B, torch, dev, pts, min(n // 4, 2000), m, k, start, variant=(1, q), label="npdu-q%d" % q)
 
 
+def test_npdu_narrow_window_edges(B, torch_dev):
+    """One-wave NPDU for windows of at most two blocks (k <= 64): sectors of
+    exactly 4096 points (the window's second block is past the last lane),
+    windows touching either end, exact ties, every point sampled, k on both
+    sides of 64, and sectors of one or two blocks."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(77)
+    full = synth.object_cloud(4096, seed=11)
+    ties = rng.integers(0, 3, (4096, 3)).astype(np.float32)
+    for pts, c, m, k, start in [(full, 4096, 1, 64, 4095), (full, 1500, 1, 63, 4095),
+                                (full, 1500, 1, 65, 4095), (full, 2000, 1, 1, 0),
+                                (full, 2000, 1, 0, 2048), (full, 4096, 1, 2, 0),
+                                (ties, 4096, 1, 64, 4000), (ties, 3000, 1, 31, 64),
+                                (full, 4096, 2, 64, 4095)]:
+        _check(B, torch, dev, pts, c, m, k, start, variant=(1, 1) if m == 1 else None,
+               label="narrow")
+    for n in (1, 2, 63, 64, 65, 127, 128, 129):
+        pts = rng.random((n, 3), dtype=np.float32)
+        for k in (0, 1, 64):
+            _check(B, torch, dev, pts, n, 1, k, n - 1, label="narrow-small")
+
+
 def test_config1_plain_fps(B, torch_dev):
     torch, dev = torch_dev
     pts = synth.uniform_cube(2048, 0)

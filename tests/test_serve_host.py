@@ -98,7 +98,8 @@ def test_launch_failure_frees_memory_and_others_complete():
 def test_slots_are_reused_under_a_small_budget():
     clock = FakeClock()
     ex = FakeExecutor(clock)
-    one = sum(-(-x // ALIGN) * ALIGN for x in footprint(_req(0, 60000, 0))) + 2 * ALIGN
+    blocks = list(footprint(_req(0, 60000, 0))) + [library_workspace_bytes(8)]
+    one = sum(-(-x // ALIGN) * ALIGN for x in blocks)
     s = Scheduler(ex, one + ALIGN, max_inflight=4, clock=clock)   # room for one frame at a time
     reqs = [_req(i, 60000, 0.0) for i in range(5)]
     done = s.run(reqs)
