@@ -33,6 +33,10 @@
 
 namespace afps {
 
+// Points per lane whose loads are in flight together when a sampler copies
+// its sector into LDS.
+constexpr int kLoadRound = 32;
+
 // Algorithm 1 initialises every distance to 1e10 (exact in fp32).
 constexpr float kInitialDistance = 1e10f;
 
@@ -366,28 +370,22 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     };
     const uint32_t init = __float_as_uint(kInitialDistance);
 
-    // Load: sixteen points in flight per lane; indices past n read point n-1
-    // and store a padding record (D = 0, never inside a window).
-    {
-        int j = lane;
-        for (; j + 15 * 64 < np; j += 16 * 64) {
-            float v[48];
+    // Load in rounds of kLoadRound points per lane, every load of a round in
+    // flight at once (the rounds are latency bound).  Indices past n read
+    // point n-1; records past n are padding (D = 0, never inside a window).
+    for (int j0 = 0; j0 < np; j0 += kLoadRound * 64) {
+        float v[3 * kLoadRound];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int jj = min(j + 64 * u, n - 1);
-                v[3 * u] = xyz[3 * jj];
-                v[3 * u + 1] = xyz[3 * jj + 1];
-                v[3 * u + 2] = xyz[3 * jj + 2];
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int jj = j + 64 * u;
-                write(jj, jj < n ? init : 0u, v[3 * u], v[3 * u + 1], v[3 * u + 2]);
-            }
+        for (int u = 0; u < kLoadRound; ++u) {
+            const int jj = min(j0 + 64 * u + lane, n - 1);
+            v[3 * u] = xyz[3 * jj];
+            v[3 * u + 1] = xyz[3 * jj + 1];
+            v[3 * u + 2] = xyz[3 * jj + 2];
         }
-        for (; j < np; j += 64) {
-            const int jj = min(j, n - 1);
-            write(j, j < n ? init : 0u, xyz[3 * jj], xyz[3 * jj + 1], xyz[3 * jj + 2]);
+#pragma unroll
+        for (int u = 0; u < kLoadRound; ++u) {
+            const int jj = j0 + 64 * u + lane;
+            if (jj < np) write(jj, jj < n ? init : 0u, v[3 * u], v[3 * u + 1], v[3 * u + 2]);
         }
     }
     sector_lds_ready();
@@ -484,42 +482,22 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
     uint32_t* sd = lds + (XYZ_IN_LDS ? 3 * np : 0);
 
     if constexpr (XYZ_IN_LDS) {
-        int j = lane;
-        for (; j + 15 * 64 < np; j += 16 * 64) {  // sixteen points in flight per lane
-            float v[48];
+        for (int j0 = 0; j0 < np; j0 += kLoadRound * 64) {   // as in the narrow sampler
+            float v[3 * kLoadRound];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int jj = j + 64 * u;
-                const bool ok = jj < n;
-                v[3 * u] = ok ? xyz[3 * jj] : 0.f;
-                v[3 * u + 1] = ok ? xyz[3 * jj + 1] : 0.f;
-                v[3 * u + 2] = ok ? xyz[3 * jj + 2] : 0.f;
+            for (int u = 0; u < kLoadRound; ++u) {
+                const int jj = min(j0 + 64 * u + lane, n - 1);
+                v[3 * u] = xyz[3 * jj];
+                v[3 * u + 1] = xyz[3 * jj + 1];
+                v[3 * u + 2] = xyz[3 * jj + 2];
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                sx[j + 64 * u] = v[3 * u]; sy[j + 64 * u] = v[3 * u + 1]; sz[j + 64 * u] = v[3 * u + 2];
+            for (int u = 0; u < kLoadRound; ++u) {
+                const int jj = j0 + 64 * u + lane;
+                if (jj < np) {
+                    sx[jj] = v[3 * u]; sy[jj] = v[3 * u + 1]; sz[jj] = v[3 * u + 2];
+                }
             }
-        }
-        for (; j + 3 * 64 < np; j += 4 * 64) {    // then four
-            float v[12];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int jj = j + 64 * u;
-                const bool ok = jj < n;
-                v[3 * u] = ok ? xyz[3 * jj] : 0.f;
-                v[3 * u + 1] = ok ? xyz[3 * jj + 1] : 0.f;
-                v[3 * u + 2] = ok ? xyz[3 * jj + 2] : 0.f;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                sx[j + 64 * u] = v[3 * u]; sy[j + 64 * u] = v[3 * u + 1]; sz[j + 64 * u] = v[3 * u + 2];
-            }
-        }
-        for (; j < np; j += 64) {
-            const bool ok = j < n;
-            sx[j] = ok ? xyz[3 * j] : 0.f;
-            sy[j] = ok ? xyz[3 * j + 1] : 0.f;
-            sz[j] = ok ? xyz[3 * j + 2] : 0.f;
         }
     }
     for (int j = lane; j < np; j += 64) sd[j] = j < n ? __float_as_uint(kInitialDistance) : 0u;
