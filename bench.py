@@ -61,6 +61,22 @@ def time_plan(torch, plan, xyz_all, out, steps, warmup, stream):
     return wall, [a.elapsed_time(b) for a, b in ev]
 
 
+def time_kernel(torch, plan, xyz_all, out, reps, stream):
+    """Duration of the plan's kernels alone: eager launches (queue reset + the
+    persistent launch, no graph), HIP events on the launch stream."""
+    plan.launch(xyz_all, out_all=out, graph=False, stream=stream)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.launch(xyz_all, out_all=out, graph=False, stream=stream)
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return ms
+
+
 def npdu_work(sizes, cs, out_np, offsets, m, k):
     """Algorithmic work of AFPS-NPDU, counted from the picks: for every
     iteration of every sector, 9 fp32 ops per distance update of the window
@@ -208,7 +224,7 @@ def counter_traffic():
     """HBM bytes per launch of the NPDU step from the committed FETCH_SIZE /
     WRITE_SIZE runs, or None when the kernel sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "persistent_npdu_kernel_batch256_traffic.json")
+    path = os.path.join(ROOT, "profiles", "pooled_npdu_kernel_batch256_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -235,17 +251,24 @@ def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
     idx = list(range(take))
 
     def one(i):
-        return oracle.afps(clouds[i], cs[i], m, k, 0)
+        t = time.perf_counter()
+        o = oracle.afps(clouds[i], cs[i], m, k, 0)
+        return o, time.perf_counter() - t
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(cores) as ex:
-        outs = list(ex.map(one, idx))
+        res = list(ex.map(one, idx))
     dt = time.perf_counter() - t0
+    outs = [o for o, _ in res]
+    per_cloud_ms = [1e3 * t for _, t in res]   # each cloud runs on one thread: its latency
     same = all(np.array_equal(outs[j], gpu_out[offsets[i]:offsets[i] + cs[i]]) for j, i in enumerate(idx))
     samples = sum(cs[i] for i in idx)
     return {"value": samples / dt, "unit": "sampled pts/s", "cores": cores, "kind": "oracle",
             "sample": "first %d of the 256 clouds (%d points, %d samples), AFPS M=%d NPDU k=%d, one cloud "
                       "per thread, %.2f s" % (take, sum(len(clouds[i]) for i in idx), samples, m, k, dt),
-            "matches_gpu": bool(same)}
+            "matches_gpu": bool(same),
+            "single_thread_ms_per_cloud": {"p50": float(np.percentile(per_cloud_ms, 50)),
+                                           "max": float(np.max(per_cloud_ms)),
+                                           "mean_points": float(np.mean([len(clouds[i]) for i in idx]))}}
 
 
 def main():
@@ -312,18 +335,21 @@ def main():
     res["batch_latency"] = {"unit": "ms", "what": "per step (whole batch of 256 clouds), HIP events",
                             "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
 
-    # Roofline of the dominant kernel (the persistent NPDU kernel is the step).
+    # Roofline of the dominant kernel (the pooled NPDU kernel is the step).
     ops, upd = npdu_work(sizes, cs, out_np, plan.offsets, M, K)
-    kern_s = float(np.mean(ev_ms)) / 1e3
+    kern_ms = time_kernel(torch, plan, xyz_all, out, max(10, args.steps), stream)
+    kern_s = float(np.mean(kern_ms)) / 1e3
     hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
     res["roofline"] = {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": VALU_PEAK_TOPS,
                        "unit": "TOPS (fp32 VALU ops)", "frac": ops / kern_s / 1e12 / VALU_PEAK_TOPS,
                        "traffic": counter_traffic(),
-                       "kernel": "persistent_npdu_kernel<1,true>",
+                       "kernel": "pooled_npdu_kernel<%d>" % plan.pool_waves,
                        "algorithmic_ops_per_launch": ops, "distance_updates_per_launch": upd,
                        "hbm_bytes_per_launch": hbm_bytes,
                        "hbm_frac": hbm_bytes / kern_s / 1e9 / HBM_PEAK_GBS,
-                       "avg_launch_ms": kern_s * 1e3}
+                       "avg_launch_ms": kern_s * 1e3,
+                       "avg_launch_what": "queue reset + pooled kernel, eager launches, HIP events on the "
+                                          "launch stream (the step's graph replay adds its launch overhead)"}
 
     if not args.no_tune:
         from paper_2208_08795_amd import autotune

@@ -26,8 +26,9 @@
  *   no fused multiply-add; initial distance 1e10; argmax ties go to the lowest
  *   index.  Results are bit-identical to a sequential evaluation of the paper's
  *   loop in that arithmetic.
- *   Preconditions not checked: coordinates finite, squared distances below
- *   1e10 (coordinate extent below 1e5).
+ *   Preconditions, not checked unless input checking is on (afps_set_checking,
+ *   or AFPS_CHECK=1 in the environment when the library loads): coordinates
+ *   finite, squared distances below 1e10 (coordinate extent below 1e5).
  *   Errors: a negative status; nothing is launched and out_idx is untouched
  *   when the arguments are rejected.  No C++ exception crosses this ABI.
  *   Every function is thread-safe.
@@ -50,7 +51,8 @@ enum afps_status {
     AFPS_ERR_WORKSPACE = -4,   /* workspace missing or smaller than required */
     AFPS_ERR_HIP = -5,         /* a HIP runtime call failed; see afps_last_error() */
     AFPS_ERR_UNSUPPORTED = -6, /* the problem exceeds what the kernels handle */
-    AFPS_ERR_DEVICE = -7       /* a kernel reported a failure (e.g. a timed-out grid barrier) */
+    AFPS_ERR_DEVICE = -7,      /* a kernel reported a failure (e.g. a timed-out grid barrier) */
+    AFPS_ERR_DATA = -8         /* input check: a non-finite coordinate, or extent too large */
 };
 
 /*
@@ -152,6 +154,14 @@ int afps_plan_graph_launch(afps_plan *plan, const float *xyz_all, int32_t *out_a
 int32_t afps_plan_items(const afps_plan *plan);
 int32_t afps_plan_launches(const afps_plan *plan);
 
+/*
+ * Waves per workgroup of the plan's pooled NPDU launch (one workgroup per CU
+ * holding the CU's LDS as 1 KB pages; 4 = one wave per SIMD, 8 = two), or 0
+ * if the plan has no NPDU sectors.  Chosen at plan creation from the plan's
+ * longest sector and total work, or by afps_set_plan_occupancy.
+ */
+int32_t afps_plan_pool_waves(const afps_plan *plan);
+
 void afps_plan_destroy(afps_plan *plan);
 
 /*
@@ -205,6 +215,26 @@ int afps_set_plan_occupancy(float waves_per_simd);
  * workgroup returns and the unfinished outputs hold -1.  Process-wide.
  */
 int afps_set_spin_limit(uint32_t polls);
+
+/*
+ * Input check of the preconditions above for one cloud of n points (DEVICE
+ * xyz): every coordinate finite, and the squared diagonal of the bounding box
+ * (which bounds every squared distance) below the initial distance 1e10 of
+ * Algorithm 1.  Reads the points once on `stream` and waits for it.  Returns
+ * AFPS_OK, or AFPS_ERR_DATA with the first offending point (or the diagonal)
+ * in afps_last_error().  The first check on a device allocates a 2 KB result
+ * buffer that the library keeps until the process ends.
+ */
+int afps_check_points(const float *xyz, int64_t n, void *stream);
+
+/*
+ * Input checking on (on != 0) or off, process-wide.  When on, every sampling
+ * call first runs afps_check_points on each of its clouds (a batch plan: each
+ * descriptor's cloud, before its launch or graph replay), so the call waits
+ * for its stream and returns AFPS_ERR_DATA without launching when a cloud
+ * fails.  Off by default; AFPS_CHECK=1 in the environment turns it on at load.
+ */
+int afps_set_checking(int32_t on);
 
 /* --------------------------------------------------------------- status */
 

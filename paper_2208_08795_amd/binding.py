@@ -64,6 +64,7 @@ def lib():
             "afps_plan_graph_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
             "afps_plan_items": ([vp], i32),
             "afps_plan_launches": ([vp], i32),
+            "afps_plan_pool_waves": ([vp], i32),
             "afps_plan_destroy": ([vp], None),
             "afps_batched_workspace_bytes": ([vp, i32], sz),
             "afps_batched": ([vp, vp, i32, vp, vp, sz, vp], ctypes.c_int),
@@ -71,6 +72,8 @@ def lib():
             "afps_tune_set": ([i32, i32, i32, i32], ctypes.c_int),
             "afps_tune_reset": ([], None),
             "afps_set_spin_limit": ([ctypes.c_uint32], ctypes.c_int),
+            "afps_check_points": ([vp, ctypes.c_int64, vp], ctypes.c_int),
+            "afps_set_checking": ([i32], ctypes.c_int),
             "afps_set_plan_occupancy": ([ctypes.c_float], ctypes.c_int),
             "afps_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "afps_last_error": ([], ctypes.c_char_p),
@@ -190,6 +193,7 @@ class BatchPlan:
         self.workspace_bytes = int(lib().afps_plan_workspace_bytes(h))
         self.items = int(lib().afps_plan_items(h))
         self.launches = int(lib().afps_plan_launches(h))
+        self.pool_waves = int(lib().afps_plan_pool_waves(h))   # waves per CU of the NPDU launch
         self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
         self.offsets = [d.out_offset for d in self.descs]
         self._uploaded = False
@@ -256,6 +260,19 @@ def set_plan_occupancy(waves_per_simd: float):
 
 def set_spin_limit(polls: int):
     _check(lib().afps_set_spin_limit(polls))
+
+
+def check_points(xyz, stream=None):
+    """Input check of one cloud (waits for the stream): raises AfpsError
+    (AFPS_ERR_DATA) if a coordinate is not finite or the squared bounding-box
+    diagonal is not below 1e10."""
+    _check_points(xyz)
+    _check(lib().afps_check_points(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], _stream_handle(stream)))
+
+
+def set_checking(on: bool):
+    """Check every cloud's preconditions before each sampling call."""
+    _check(lib().afps_set_checking(1 if on else 0))
 
 
 TUNE_DIRECT, TUNE_NPDU, TUNE_BATCH = 0, 1, 2

@@ -155,6 +155,8 @@ struct DeviceState {
     int pool_pages = 0;                      // LDS pages of one pooled-NPDU workgroup
     std::vector<hipStream_t> helpers;        // bucket streams for batch plans
     void* grid_pool = nullptr;               // grid-barrier blocks
+    CheckResult* check_buf = nullptr;        // validation results (kCheckClouds), on first use
+    std::mutex check_mu;                     // one validation at a time per device
     std::vector<hipEvent_t> grid_events;     // last user of each block
     int grid_next = 0;
 };
@@ -253,6 +255,71 @@ unsigned g_spin_limit = 1u << 22;
 // measured fastest on the batched workloads).
 float g_waves_per_simd = 0.0f;
 
+// Validate inputs before every sampling call (AFPS_CHECK=1 in the
+// environment at load, or afps_set_checking).
+bool env_checking() {
+    const char* e = std::getenv("AFPS_CHECK");
+    return e && *e && std::strcmp(e, "0") != 0;
+}
+bool g_checking = env_checking();
+
+float unkey(uint32_t k) {
+    const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    float f;
+    std::memcpy(&f, &b, sizeof(f));
+    return f;
+}
+
+// Preconditions of the distance arithmetic for each cloud [offset, offset+n)
+// of xyz_all: finite coordinates, and a squared bounding-box diagonal below
+// the initial distance 1e10 (it bounds every squared distance).  Waits for
+// the stream.  `names[i]` says which cloud a failure refers to.
+int check_clouds(const float* xyz_all, const std::vector<CheckSeg>& segs, hipStream_t stream,
+                 const std::vector<std::string>& names) {
+    DeviceState* d;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(d->check_mu);
+    if (!d->check_buf) AFPS_HIP(hipMalloc((void**)&d->check_buf, kCheckClouds * sizeof(CheckResult)));
+    CheckResult host[kCheckClouds];
+    for (size_t first = 0; first < segs.size(); first += kCheckClouds) {
+        const int count = (int)std::min<size_t>(kCheckClouds, segs.size() - first);
+        CheckBatch batch{};
+        for (int i = 0; i < count; ++i) batch.seg[i] = segs[first + i];
+        CheckResult* buf = d->check_buf;
+        void* args[] = {(void*)&xyz_all, &batch, &buf};
+        AFPS_HIP(hipLaunchKernel(check_points_kernel(), dim3(count), dim3(256), args, 0, stream));
+        AFPS_HIP(hipMemcpyAsync(host, buf, count * sizeof(CheckResult), hipMemcpyDeviceToHost, stream));
+        AFPS_HIP(hipStreamSynchronize(stream));
+        for (int i = 0; i < count; ++i) {
+            const CheckResult& r = host[i];
+            const std::string& who = names[first + i];
+            if (r.first_bad != ~0ull)
+                return fail(AFPS_ERR_DATA, who + "point " + std::to_string(r.first_bad) +
+                                               " has a non-finite coordinate");
+            if (segs[first + i].n == 0) continue;
+            double diag2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double e = (double)unkey(r.hi[a]) - (double)unkey(r.lo[a]);
+                diag2 += e * e;
+            }
+            if (diag2 >= 1e10) {
+                char msg[160];
+                std::snprintf(msg, sizeof(msg),
+                              "squared bounding-box diagonal %.6g is not below the initial distance 1e10",
+                              diag2);
+                return fail(AFPS_ERR_DATA, who + msg);
+            }
+        }
+    }
+    return AFPS_OK;
+}
+
+int maybe_check_cloud(const float* xyz, int32_t n, void* stream) {
+    if (!g_checking) return AFPS_OK;
+    return check_clouds(xyz, {CheckSeg{0, n, 0}}, (hipStream_t)stream, {""});
+}
+
 int launch_grid_fps(const float* xyz, int32_t n, int32_t c, int32_t start, int32_t* out,
                      hipStream_t stream) {
     const GridVariant* gv = nullptr;
@@ -321,6 +388,7 @@ const char* afps_status_string(int status) {
         case AFPS_ERR_HIP: return "HIP runtime error";
         case AFPS_ERR_UNSUPPORTED: return "problem exceeds the kernels' capacity";
         case AFPS_ERR_DEVICE: return "device-side failure";
+        case AFPS_ERR_DATA: return "input coordinates violate the preconditions";
         default: return "unknown status";
     }
 }
@@ -329,14 +397,17 @@ const char* afps_last_error(void) { return g_last_error.c_str(); }
 
 int32_t afps_max_sector_points(void) { return kMaxFullSector; }
 
-int afps_afps(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t start, int32_t* out_idx,
+}  // extern "C"
+
+namespace {
+
+// afps_afps after argument validation (and the optional input check).
+int afps_impl(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t start, int32_t* out_idx,
               void* stream) {
-    if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
-    int rc = check_sizes(n, c, m, start);
-    if (rc) return rc;
+    int rc;
     const int32_t ns = largest_sector(n, m);
     if (ns > kMaxFullSector) {
-        if (m == 1) return afps_fps_plain(xyz, n, c, start, out_idx, stream);
+        if (m == 1) return launch_grid_fps(xyz, n, c, start, out_idx, (hipStream_t)stream);
         return fail(AFPS_ERR_UNSUPPORTED, "sector of " + std::to_string(ns) +
                                               " points exceeds one workgroup (use more sectors)");
     }
@@ -345,6 +416,19 @@ int afps_afps(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t start, 
     const VariantEntry* v = choose_full(ns);
     if (!v) return fail(AFPS_ERR_UNSUPPORTED, "no kernel variant holds the sector");
     return launch_full_direct(*v, xyz, n, c, m, start, out_idx, (hipStream_t)stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int afps_afps(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t start, int32_t* out_idx,
+              void* stream) {
+    if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
+    int rc = check_sizes(n, c, m, start);
+    if (rc) return rc;
+    if ((rc = maybe_check_cloud(xyz, n, stream))) return rc;
+    return afps_impl(xyz, n, c, m, start, out_idx, stream);
 }
 
 int afps_afps_npdu(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
@@ -358,6 +442,7 @@ int afps_afps_npdu(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k,
     if (!v)
         return fail(AFPS_ERR_UNSUPPORTED, "NPDU sector of " + std::to_string(ns) +
                                               " points exceeds one workgroup (use more sectors)");
+    if ((rc = maybe_check_cloud(xyz, n, stream))) return rc;
     DeviceState* d;
     if ((rc = device_state(&d))) return rc;
     return launch_npdu_direct(*v, xyz, n, c, m, clamp_k(k, ns), start, out_idx, (hipStream_t)stream);
@@ -368,8 +453,8 @@ int afps_fps_plain(const float* xyz, int32_t n, int32_t c, int32_t start, int32_
     if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
     int rc = check_sizes(n, c, 1, start);
     if (rc) return rc;
-    if (n <= kMaxFullSector) return afps_afps(xyz, n, c, 1, start, out_idx, stream);
-    return launch_grid_fps(xyz, n, c, start, out_idx, (hipStream_t)stream);
+    if ((rc = maybe_check_cloud(xyz, n, stream))) return rc;
+    return afps_impl(xyz, n, c, 1, start, out_idx, stream);
 }
 
 int afps_afps_variant(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
@@ -377,6 +462,7 @@ int afps_afps_variant(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t
     if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
     int rc = check_sizes(n, c, m, start);
     if (rc) return rc;
+    if ((rc = maybe_check_cloud(xyz, n, stream))) return rc;
     const int32_t ns = largest_sector(n, m);
     DeviceState* d;
     if ((rc = device_state(&d))) return rc;
@@ -439,6 +525,18 @@ int afps_set_plan_occupancy(float waves_per_simd) {
     return AFPS_OK;
 }
 
+int afps_check_points(const float* xyz, int64_t n, void* stream) {
+    if (!xyz) return fail(AFPS_ERR_NULL, "xyz must be non-null");
+    if (n < 0 || n > INT32_MAX) return fail(AFPS_ERR_ARG, "n must be in [0, 2^31-1]");
+    if (n == 0) return AFPS_OK;
+    return check_clouds(xyz, {CheckSeg{0, (int32_t)n, 0}}, (hipStream_t)stream, {""});
+}
+
+int afps_set_checking(int32_t on) {
+    g_checking = on != 0;
+    return AFPS_OK;
+}
+
 int afps_set_spin_limit(uint32_t polls) {
     if (polls == 0) return fail(AFPS_ERR_ARG, "spin limit must be positive");
     g_spin_limit = polls;
@@ -481,6 +579,7 @@ struct afps_plan {
     std::vector<WorkItem> items;
     std::vector<Bucket> buckets;
     std::vector<PoolQueue> queues;    // pool queues, highest priority first
+    std::vector<CheckSeg> clouds;     // each descriptor's points, for the optional input check
     int pool_pages = 0;
     size_t ws_bytes = 0;
     int device = 0;
@@ -521,6 +620,7 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             return fail(AFPS_ERR_ARG, where + "negative offset or nonzero reserved field");
         int rc = check_sizes(d.n, d.c, d.m, d.start);
         if (rc) return fail(rc, where + g_last_error);
+        plan->clouds.push_back(CheckSeg{d.xyz_offset, d.n, 0});
         const int32_t qn = d.n / d.m, rn = d.n % d.m, qc = d.c / d.m, rc_ = d.c % d.m;
         for (int32_t s = 0; s < d.m; ++s) {
             Staged st{};
@@ -737,6 +837,13 @@ int32_t afps_plan_items(const afps_plan* plan) { return plan ? (int32_t)plan->it
 
 int32_t afps_plan_launches(const afps_plan* plan) { return plan ? (int32_t)plan->buckets.size() : 0; }
 
+int32_t afps_plan_pool_waves(const afps_plan* plan) {
+    if (!plan) return 0;
+    for (const auto& bk : plan->buckets)
+        if (bk.pool) return bk.block / 64;
+    return 0;
+}
+
 void afps_plan_destroy(afps_plan* plan) { delete plan; }
 
 int afps_plan_upload(afps_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
@@ -756,13 +863,19 @@ int afps_plan_upload(afps_plan* plan, void* workspace, size_t workspace_bytes, v
     return AFPS_OK;
 }
 
-int afps_plan_launch(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
-                     void* stream_) {
-    if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
-    if (plan->items.empty()) return AFPS_OK;
-    if (!xyz_all || !out_all) return fail(AFPS_ERR_NULL, "xyz_all and out_all must be non-null");
-    if (!workspace) return fail(AFPS_ERR_WORKSPACE, "workspace must be non-null");
-    hipStream_t stream = (hipStream_t)stream_;
+}  // extern "C"
+
+namespace {
+
+int check_plan_clouds(const afps_plan* plan, const float* xyz_all, hipStream_t stream) {
+    std::vector<std::string> names;
+    for (size_t i = 0; i < plan->clouds.size(); ++i) names.push_back("cloud " + std::to_string(i) + ": ");
+    return check_clouds(xyz_all, plan->clouds, stream, names);
+}
+
+// afps_plan_launch after argument checks: launches only (capturable).
+int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
+                     hipStream_t stream) {
     unsigned* counters = (unsigned*)workspace;
     unsigned* qtaken = (unsigned*)((char*)workspace + kPoolCounterOffset);
     const PoolQueue* queues = (const PoolQueue*)((char*)workspace + kPoolTableOffset);
@@ -810,11 +923,34 @@ int afps_plan_launch(const afps_plan* plan, const float* xyz_all, int32_t* out_a
     return AFPS_OK;
 }
 
-int afps_plan_graph_launch(afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
-                           void* stream_) {
+int plan_launch_args(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace) {
     if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
     if (plan->items.empty()) return AFPS_OK;
+    if (!xyz_all || !out_all) return fail(AFPS_ERR_NULL, "xyz_all and out_all must be non-null");
+    if (!workspace) return fail(AFPS_ERR_WORKSPACE, "workspace must be non-null");
+    return AFPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int afps_plan_launch(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
+                     void* stream) {
+    int rc = plan_launch_args(plan, xyz_all, out_all, workspace);
+    if (rc || plan->items.empty()) return rc;
+    if (g_checking && (rc = check_plan_clouds(plan, xyz_all, (hipStream_t)stream))) return rc;
+    return plan_launch_impl(plan, xyz_all, out_all, workspace, (hipStream_t)stream);
+}
+
+int afps_plan_graph_launch(afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
+                           void* stream_) {
+    int rc0 = plan_launch_args(plan, xyz_all, out_all, workspace);
+    if (rc0 || plan->items.empty()) return rc0;
     hipStream_t stream = (hipStream_t)stream_;
+    // The check synchronises the stream, so it runs before the replay, never
+    // inside the capture.
+    if (g_checking && (rc0 = check_plan_clouds(plan, xyz_all, stream))) return rc0;
     std::lock_guard<std::mutex> lk(plan->mu);
     if (!plan->exec || plan->g_xyz != xyz_all || plan->g_out != out_all || plan->g_ws != workspace) {
         if (plan->exec) {
@@ -825,7 +961,7 @@ int afps_plan_graph_launch(afps_plan* plan, const float* xyz_all, int32_t* out_a
         // stream, which cannot be captured); replay on the caller's stream.
         if (!plan->capture) AFPS_HIP(hipStreamCreateWithFlags(&plan->capture, hipStreamNonBlocking));
         AFPS_HIP(hipStreamBeginCapture(plan->capture, hipStreamCaptureModeThreadLocal));
-        int rc = afps_plan_launch(plan, xyz_all, out_all, workspace, plan->capture);
+        int rc = plan_launch_impl(plan, xyz_all, out_all, workspace, plan->capture);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(plan->capture, &graph);
         if (rc) {

@@ -82,6 +82,25 @@ __host__ __device__ constexpr int npdu_pool_pages(int n) {
     return (4 * npdu_lds_words(n, npdu_r_for(n) <= 2) + kPoolPageBytes - 1) / kPoolPageBytes;
 }
 
+// Point validation pass (check.hip): one workgroup per cloud, up to
+// kCheckClouds clouds per launch; per cloud the first point with a non-finite
+// coordinate and the order keys of the smallest and largest x, y, z.
+struct CheckSeg {
+    int64_t offset;   // first point of the cloud, in points
+    int32_t n;
+    int32_t pad;
+};
+constexpr int kCheckClouds = 64;
+struct CheckBatch {
+    CheckSeg seg[kCheckClouds];   // passed by value (1 KB of kernel arguments)
+};
+struct CheckResult {
+    unsigned long long first_bad;   // ~0 if every coordinate is finite
+    uint32_t lo[3], hi[3];          // order keys: unsigned order of the keys = float order
+};
+static_assert(sizeof(CheckResult) == 32, "check result layout");
+const void* check_points_kernel();
+
 // Multi-workgroup plain FPS (fps_grid.hip).
 struct GridVariant {
     int waves, slots;

@@ -34,7 +34,7 @@ def test_exports_every_declared_function(L):
 
 def test_status_strings(L):
     from paper_2208_08795_amd import binding
-    for st in range(0, -8, -1):
+    for st in range(0, -9, -1):
         assert binding.status_string(st) not in ("", "unknown status")
     assert binding.status_string(-99) == "unknown status"
 
@@ -53,6 +53,10 @@ def test_host_validation_without_gpu(L):
     assert L.afps_fps_plain(dummy, 0, 0, 0, dummy, None) == -2
     assert "1 <= m <= c <= n" in L.afps_last_error().decode()
     assert L.afps_set_spin_limit(0) == -2
+    assert L.afps_check_points(None, 10, None) == -1
+    assert L.afps_check_points(dummy, -1, None) == -2
+    assert L.afps_check_points(dummy, 0, None) == 0          # empty cloud: nothing to read
+    assert L.afps_set_checking(0) == 0
     # bad descriptors are rejected before any device work
     descs, _, _ = binding.descriptors([100, 50], [10, 60], [2, 1], [None, 4], [0, 0])
     plan = ctypes.c_void_p()
