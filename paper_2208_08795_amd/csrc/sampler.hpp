@@ -391,25 +391,30 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     sector_lds_ready();
 
     // Lanes past the last block hold 0: a lower lane holds a value >= 0, so
-    // they never win the lowest-lane search below.
+    // they never win the lowest-lane search below.  bi holds, per block, the
+    // position inside the block of its lowest-index maximum.
     uint32_t bm = lane < nb ? init : 0u;
-    uint32_t bi = (uint32_t)(64 * lane);
+    uint32_t bi = 0u;
     const int below = k >> 1, above = k - (k >> 1);
-    uint32_t picks = (uint32_t)(base + cur);   // pick i in lane i mod 64, written 64 at a time
+    uint32_t* const rec_lane = rec + 4 * lane;   // this lane's record in block 0
+    uint32_t picks = (uint32_t)cur;               // sector-local pick of step s in lane s
 
-    for (int i = 1; i < c; ++i) {
+    // One iteration of the loop: the new sample's record, the two blocks
+    // holding its window, their update and re-reduction, the next sample.
+    auto step = [&](int s) {
+        const uint4 P = read(cur);
         const int lo = max(0, cur - below);
         const int hi = min(n - 1, cur + above);
         const int blo = lo >> 6;
-        const int j0 = 64 * blo + lane;
-        const uint4 P = read(cur);
-        const uint4 A = read(j0);
-        const uint4 B = read(j0 + 64);
+        uint32_t* const wb = rec_lane + 256 * blo;   // this lane's record in block blo
+        uint4 A, B;
+        __builtin_memcpy(&A, wb, 16);
+        __builtin_memcpy(&B, wb + 256, 16);
 
         const uint32_t g_out = wave_max((uint32_t)(lane - blo) > 1u ? bm : 0u);
 
-        // Window: point j0 is in it iff 0 <= t <= hi - lo, point j0 + 64 iff
-        // t + 64 <= hi - lo, with t = j0 - lo.
+        // Window: A's point is in it iff 0 <= t <= hi - lo, B's iff
+        // t + 64 <= hi - lo, with t = (64 blo + lane) - lo.
         const int t = lane - (lo & 63);
         const int span = hi - lo;
         const float px = __uint_as_float(P.y), py = __uint_as_float(P.z), pz = __uint_as_float(P.w);
@@ -419,13 +424,13 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
                                                   __uint_as_float(B.w), px, py, pz));
         const uint32_t d0 = (uint32_t)t <= (uint32_t)span ? e0 : A.x;
         const uint32_t d1 = t <= span - 64 ? e1 : B.x;
-        rec[4 * j0] = d0;
-        rec[4 * (j0 + 64)] = d1;
+        wb[0] = d0;
+        wb[256] = d1;
 
         uint32_t g0, g1;
         wave_max2(d0, d1, g0, g1);
-        const uint32_t i0 = (uint32_t)(64 * blo) + (uint32_t)__builtin_ctzll(ballot(d0 == g0));
-        const uint32_t i1 = (uint32_t)(64 * blo + 64) + (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+        const uint32_t i0 = (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+        const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
         // Block blo+1 may be the padding block (g1 = 0) or, for n = 4096,
         // lane 64, which does not exist: then it goes to lane 63 first and
         // block blo = 63 overwrites it.
@@ -436,12 +441,24 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
         bi = writelane(bi, i0, blo);
 
         const uint32_t g = max(g_out, max(g0, g1));
-        cur = (int)readlane(bi, (int)__builtin_ctzll(ballot(bm == g)));
-        picks = writelane(picks, (uint32_t)(base + cur), i & 63);
-        if ((i & 63) == 63) out[i - 63 + lane] = (int32_t)picks;
+        const int wl = (int)__builtin_ctzll(ballot(bm == g));
+        cur = 64 * wl + (int)readlane(bi, wl);
+        picks = writelane(picks, (uint32_t)cur, s);
+    };
+
+    // Picks go out 64 at a time.  The loop is bound by instruction issue
+    // (one wave): two steps per trip, and a loop counter kept scalar, save
+    // the counter and branch work of every other step.
+    for (int i0 = 0; i0 < c; i0 += 64) {
+        const int s_end = min(64, c - i0);
+        int s = i0 == 0 ? 1 : 0;                  // step 0 of the sector is its start
+        for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
+            step(s);
+            step(s + 1);
+        }
+        if (s < s_end) step(s);
+        if (lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
     }
-    const int tail = (c - 1) & 63;   // picks of the last, partial group
-    if (tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
 }
 
 // NPDU on one sector (Sec. III-C), one wave.
