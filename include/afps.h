@@ -109,35 +109,40 @@ typedef struct afps_plan afps_plan;
 /*
  * Build a batch plan on the host from `batch` HOST descriptors: validates
  * them, expands every cloud into its sectors (work items), orders the items
- * longest-first, groups them by kernel variant and sizes the workspace.
+ * longest-first, and groups them: NPDU sectors into queues by LDS pages (one
+ * pooled launch), FPS/AFPS sectors by kernel variant (one persistent launch
+ * each); sizes the workspace.
  * Returns AFPS_OK and *plan, or an error (AFPS_ERR_ARG names the first bad
  * descriptor in afps_last_error()).
  */
 int afps_plan_create(const afps_cloud_desc *descs, int32_t batch, afps_plan **plan);
 
-/* Device workspace bytes the plan needs (work items + queue counters). */
+/* Device workspace bytes the plan needs (counters, queue table, work items). */
 size_t afps_plan_workspace_bytes(const afps_plan *plan);
 
 /*
  * Workspace bytes of a plan with `items` work items in total (one per sector,
- * i.e. the sum of m over the batch): queue counters plus the item table,
- * rounded up to 256.  Lets a caller reserve device memory before building
+ * i.e. the sum of m over the batch): a 2.75 KB header of queue counters and
+ * the NPDU queue table plus 40 bytes per item, rounded up to 256.  Lets a caller reserve device memory before building
  * the plan.  Host-only arithmetic; 0 for items <= 0.
  */
 size_t afps_workspace_bytes_for_items(int32_t items);
 
 /*
- * Copy the plan's work-item table into `workspace` (DEVICE, >= the size
- * above, 256-byte aligned) on `stream`.  Must precede afps_plan_launch with
- * that workspace; the table stays valid until overwritten.
+ * Copy the plan's tables (NPDU queues, work items) into `workspace` (DEVICE,
+ * >= the size above, 256-byte aligned) on `stream`.  Must precede
+ * afps_plan_launch with that workspace; the tables stay valid until
+ * overwritten.
  */
 int afps_plan_upload(afps_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Run the batch: reset the queue counters, then one persistent launch per
- * kernel variant; each workgroup takes work items from a device queue with an
- * atomic counter until the queue is empty.  Kernel launches only, so a
- * caller may capture it in a hipGraph.
+ * Run the batch: reset the queue counters (a kernel), then one persistent
+ * launch per kernel variant, concurrent on helper streams when there are
+ * several; workgroups (NPDU: waves) take work items from device queues with
+ * atomic counters until the queues are empty.  Kernel launches only, so a
+ * caller may capture it in a hipGraph.  Launches with one workspace must not
+ * overlap.
  */
 int afps_plan_launch(const afps_plan *plan, const float *xyz_all, int32_t *out_all,
                      void *workspace, void *stream);

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
             __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // the previous owner's accesses are done
+        spins = 0;                                                // the limit bounds each wait
 
         const WorkItem wi = items[item];
         run_item(xyz_all, out_all, wi, pool + s * (kPoolPageBytes / 4));

@@ -257,6 +257,41 @@ def test_grid_barrier_timeout_is_bounded(B, torch_dev):
     assert np.all(got[f:] == -1)
 
 
+def test_pool_wait_timeout_fails_whole_sectors_and_resets(B, torch_dev):
+    """A spin limit of 1 makes waves of the pooled NPDU kernel give up on the
+    allocation lock or on pages: every sector must then be either exact or
+    entirely -1 (no sector half written), and the next launch of the same plan
+    (counters left reset by the failed one) must be exact again."""
+    torch, dev = torch_dev
+    clouds = synth.batch_of_objects(64, seed=9, n_min=2048, n_max=32768)
+    cs = [len(p) // 4 for p in clouds]
+    m = [8] * len(clouds)
+    plan = B.BatchPlan([len(p) for p in clouds], cs, m, [32] * len(clouds), [0] * len(clouds), device=dev)
+    xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    want = [oracle.afps(p, c, 8, 32, 0) for p, c in zip(clouds, cs)]
+    try:
+        B.set_spin_limit(1)
+        out = plan.launch(xyz)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for i, (c, w) in enumerate(zip(cs, want)):
+            g = got[plan.offsets[i]:plan.offsets[i] + c]
+            qn, rn, qc, rc = len(clouds[i]) // 8, len(clouds[i]) % 8, c // 8, c % 8
+            for s in range(8):
+                o, cc = s * qc + min(s, rc), qc + (s < rc)
+                sector = g[o:o + cc]
+                assert np.array_equal(sector, w[o:o + cc]) or np.all(sector == -1), (i, s)
+    finally:
+        B.set_spin_limit(1 << 22)
+    for graph in (False, True):
+        out = plan.launch(xyz, graph=graph)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for i, (c, w) in enumerate(zip(cs, want)):
+            assert np.array_equal(got[plan.offsets[i]:plan.offsets[i] + c], w), (graph, i)
+    plan.close()
+
+
 def test_autotuner_choices_stay_exact(B, torch_dev):
     """The autotuner installs its fastest variants; sampling with them still
     gives the oracle's indices (direct launches and batch plans)."""
