@@ -51,6 +51,8 @@ def load(path: str | None = None):
         fptr, iptr = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)
         lib.oracle_afps.argtypes = [fptr, i32, i32, i32, i32, i32, iptr, fptr, i64p]
         lib.oracle_afps.restype = ctypes.c_int
+        lib.oracle_afps_ex.argtypes = [fptr, i32, i32, i32, i32, i32, i32, iptr, fptr, i64p]
+        lib.oracle_afps_ex.restype = ctypes.c_int
         lib.oracle_fps.argtypes = [fptr, i32, i32, i32, iptr, fptr, i64p]
         lib.oracle_fps.restype = ctypes.c_int
         lib.oracle_sector.argtypes = [i32, i32, i32, i32, iptr, iptr, iptr, iptr]
@@ -71,13 +73,17 @@ def _points(points) -> np.ndarray:
     return p
 
 
+# NPDU readings other than the default (bit flags; see afps_oracle.c).
+NPDU_FIRST_FULL, NPDU_SHIFT_EDGES, NPDU_K_WITH_SELF = 1, 2, 4
+
+
 def afps(points, c: int, m: int = 1, k: int | None = None, start: int = 0,
-         with_state: bool = False, lib=None):
+         with_state: bool = False, lib=None, flags: int = 0):
     """AFPS (Sec. III-B) with M sectors, NPDU window k (Sec. III-C) or None.
 
     Returns int32 global indices (sector-major, pick order inside a sector).
     With ``with_state`` also returns the final Distance array and the number of
-    distance evaluations.
+    distance evaluations.  ``flags`` selects NPDU readings (NPDU_*).
     """
     lib = lib or load()
     p = _points(points)
@@ -85,9 +91,9 @@ def afps(points, c: int, m: int = 1, k: int | None = None, start: int = 0,
     out = np.empty(max(c, 0), dtype=np.int32)
     dist = np.empty(max(n, 0), dtype=np.float32)
     evals = ctypes.c_int64(0)
-    rc = lib.oracle_afps(
+    rc = lib.oracle_afps_ex(
         p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, c, m,
-        -1 if k is None else int(k), start,
+        -1 if k is None else int(k), int(flags), start,
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         dist.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(evals))
     if rc != 0:

@@ -30,6 +30,8 @@
  *     there is no full distance pass on the first iteration;
  *   - the last sample's own distance update is never applied (Algorithm 1 ends
  *     after storing the last sample).
+ * The alternative readings of the three NPDU points are available as flags
+ * (ORACLE_NPDU_* below), so that their effect can be measured.
  *
  * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math
  * (x86-64 SSE arithmetic: every fp32 operation is a single IEEE rounding).
@@ -42,6 +44,23 @@
 #define ORACLE_ERR_ARG (-2)
 #define ORACLE_ERR_RANGE (-3)
 #define ORACLE_ERR_NOMEM (-6)
+
+/*
+ * NPDU readings other than the default one (bit flags), for the points
+ * Sec. III-C leaves open:
+ *   FIRST_FULL : the first iteration updates every point of the sector (one
+ *                full Algorithm-1 update from the start point); later
+ *                iterations update only the window;
+ *   SHIFT_EDGES: a window that would cross an edge of the sector is moved
+ *                inward, keeping its size as far as the sector allows,
+ *                instead of being truncated;
+ *   K_WITH_SELF: the k updated points include the new sample: floor((k-1)/2)
+ *                below it and ceil((k-1)/2) above (k >= 1), instead of the
+ *                sample plus k neighbours.
+ */
+#define ORACLE_NPDU_FIRST_FULL 1
+#define ORACLE_NPDU_SHIFT_EDGES 2
+#define ORACLE_NPDU_K_WITH_SELF 4
 
 /* Algorithm 1: every distance starts at 1e10. */
 static const float INITIAL_DISTANCE = 1e10f;
@@ -83,7 +102,7 @@ static float squared_distance(const float *p, const float *q)
  * distance evaluations.
  */
 static int64_t sample_sector(const float *P, int32_t first, int32_t n, int32_t c,
-                             int32_t k, int32_t start, float *dist, int32_t *out)
+                             int32_t k, int32_t flags, int32_t start, float *dist, int32_t *out)
 {
     int64_t evaluations = 0;
     for (int32_t j = 0; j < n; ++j)
@@ -95,10 +114,28 @@ static int64_t sample_sector(const float *P, int32_t first, int32_t n, int32_t c
     for (int32_t i = 1; i < c; ++i) {                  /* Algorithm 1: i = 1 .. n_point-1 */
         /* Update set: the whole sector (FPS / AFPS), or the NPDU window. */
         int32_t lo = 0, hi = n - 1;
-        if (k >= 0) {
-            int32_t below = k / 2, above = k - k / 2;
-            lo = cur - below < 0 ? 0 : cur - below;
-            hi = (int64_t)cur + above > (int64_t)(n - 1) ? n - 1 : cur + above;
+        if (k >= 0 && !(i == 1 && (flags & ORACLE_NPDU_FIRST_FULL))) {
+            int32_t below, above;
+            if (flags & ORACLE_NPDU_K_WITH_SELF) {
+                below = (k - 1) / 2;                   /* k >= 1: k points with the sample */
+                above = (k - 1) - below;
+            } else {
+                below = k / 2;                         /* the sample and k neighbours */
+                above = k - k / 2;
+            }
+            int64_t l = (int64_t)cur - below, h = (int64_t)cur + above;
+            if (flags & ORACLE_NPDU_SHIFT_EDGES) {
+                if (l < 0) {                           /* move right, off the lower edge */
+                    h -= l;
+                    l = 0;
+                }
+                if (h > n - 1) {                       /* move left, off the upper edge */
+                    l -= h - (n - 1);
+                    h = n - 1;
+                }
+            }
+            lo = l < 0 ? 0 : (int32_t)l;               /* truncate to the sector */
+            hi = h > n - 1 ? n - 1 : (int32_t)h;
         }
         const float *sample = P + 3 * (int64_t)(first + cur);
         for (int32_t j = lo; j <= hi; ++j) {           /* Algorithm 1: distance update */
@@ -118,7 +155,8 @@ static int64_t sample_sector(const float *P, int32_t first, int32_t n, int32_t c
 }
 
 /*
- * AFPS with M sectors; k < 0 turns NPDU off; M = 1 and k < 0 is plain FPS.
+ * AFPS with M sectors; k < 0 turns NPDU off; M = 1 and k < 0 is plain FPS;
+ * flags selects NPDU readings (ORACLE_NPDU_*; 0 = the default reading).
  *   P      : n x 3 fp32, row-major (x, y, z per point)
  *   out    : c int32 global indices, sector-major, pick order inside a sector
  *   dist   : optional (may be NULL), n floats: the Distance arrays as the loop
@@ -126,12 +164,18 @@ static int64_t sample_sector(const float *P, int32_t first, int32_t n, int32_t c
  *   evals  : optional (may be NULL), total number of distance evaluations
  * Requires 1 <= m <= c <= n and 0 <= start < n.
  */
-int oracle_afps(const float *P, int32_t n, int32_t c, int32_t m, int32_t k,
-                int32_t start, int32_t *out, float *dist, int64_t *evals)
+int oracle_afps_ex(const float *P, int32_t n, int32_t c, int32_t m, int32_t k, int32_t flags,
+                   int32_t start, int32_t *out, float *dist, int64_t *evals)
 {
     if (!P || !out)
         return ORACLE_ERR_NULL;
     if (m < 1 || c < m || n < c)
+        return ORACLE_ERR_ARG;
+    if (flags & ~(ORACLE_NPDU_FIRST_FULL | ORACLE_NPDU_SHIFT_EDGES | ORACLE_NPDU_K_WITH_SELF))
+        return ORACLE_ERR_ARG;
+    if (flags && k < 0)
+        return ORACLE_ERR_ARG;                         /* the flags are NPDU readings */
+    if ((flags & ORACLE_NPDU_K_WITH_SELF) && k < 1)
         return ORACLE_ERR_ARG;
     if (start < 0 || start >= n)
         return ORACLE_ERR_RANGE;
@@ -146,7 +190,7 @@ int oracle_afps(const float *P, int32_t n, int32_t c, int32_t m, int32_t k,
     for (int32_t s = 0; s < m; ++s) {                  /* sectors are independent */
         int32_t first, count, first_out, samples;
         oracle_sector(n, c, m, s, &first, &count, &first_out, &samples);
-        total += sample_sector(P, first, count, samples, k, start,
+        total += sample_sector(P, first, count, samples, k, flags, start,
                                work + first, out + first_out);
     }
     if (work != dist)
@@ -154,6 +198,13 @@ int oracle_afps(const float *P, int32_t n, int32_t c, int32_t m, int32_t k,
     if (evals)
         *evals = total;
     return ORACLE_OK;
+}
+
+/* AFPS / NPDU with the default readings. */
+int oracle_afps(const float *P, int32_t n, int32_t c, int32_t m, int32_t k,
+                int32_t start, int32_t *out, float *dist, int64_t *evals)
+{
+    return oracle_afps_ex(P, n, c, m, k, 0, start, out, dist, evals);
 }
 
 /* Plain FPS (Algorithm 1): AFPS with one sector and no NPDU. */

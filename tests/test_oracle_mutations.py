@@ -27,13 +27,19 @@ MUTANTS = {
                            "*first_sample = s * qc + (s < rc ? 0 : rc);"),
     "point_split_last": ("*num_points = qn + (s < rn ? 1 : 0);",
                          "*num_points = qn + (s >= m - rn ? 1 : 0);"),
-    "window_floor_ceil_swapped": ("int32_t below = k / 2, above = k - k / 2;",
-                                  "int32_t below = k - k / 2, above = k / 2;"),
-    "window_excludes_top": ("? n - 1 : cur + above;", "? n - 1 : cur + above - 1;"),
+    "window_floor_ceil_swapped": ("below = k / 2;                         /* the sample and k neighbours */\n                above = k - k / 2;",
+                                  "below = k - k / 2;\n                above = k / 2;"),
+    "window_excludes_top": ("hi = h > n - 1 ? n - 1 : (int32_t)h;", "hi = h > n - 1 ? n - 1 : (int32_t)h - 1;"),
     "start_not_local": ("int32_t cur = start % n;", "int32_t cur = 0;"),
     "initial_1e9": ("INITIAL_DISTANCE = 1e10f;", "INITIAL_DISTANCE = 1e9f;"),
     "local_output_index": ("out[i] = first + cur;", "out[i] = cur;"),
-    "npdu_full_first_pass": ("if (k >= 0) {", "if (k >= 0 && i > 1) {"),
+    "npdu_full_first_pass": ("if (k >= 0 && !(i == 1 && (flags & ORACLE_NPDU_FIRST_FULL))) {",
+                             "if (k >= 0 && i > 1) {"),
+    "first_full_every_iteration": ("!(i == 1 && (flags & ORACLE_NPDU_FIRST_FULL))",
+                                   "!(flags & ORACLE_NPDU_FIRST_FULL)"),
+    "shift_wrong_way": ("                    h -= l;", "                    h += l;"),
+    "shift_never_left": ("                    l -= h - (n - 1);", "                    l -= 0;"),
+    "self_window_not_reduced": ("below = (k - 1) / 2;", "below = k / 2;"),
 }
 
 
@@ -42,7 +48,8 @@ def _pins_pass(lib) -> bool:
         for case in json.load(f)["cases"]:
             pts = np.array(case["points"], dtype=np.float32)
             try:
-                got = oracle.afps(pts, case["c"], case["m"], case["k"], case["start"], lib=lib)
+                got = oracle.afps(pts, case["c"], case["m"], case["k"], case["start"], lib=lib,
+                                  flags=case.get("flags", 0))
             except oracle.OracleError:
                 return False
             if got.tolist() != case["expected"]:
@@ -61,6 +68,20 @@ def _pins_pass(lib) -> bool:
             return False
         if got.tolist() != bruteforce.afps(pts, c, m, k, start).tolist():
             return False
+    for flags in (1, 2, 4, 7):                  # the alternative NPDU readings
+        for _ in range(12):
+            n = int(rng.integers(2, 40))
+            pts = rng.random((n, 3), dtype=np.float32)
+            c = int(rng.integers(1, n + 1))
+            m = int(rng.integers(1, c + 1))
+            k = [1, 2, 3, 6][int(rng.integers(0, 4))]
+            start = int(rng.integers(0, n))
+            try:
+                got = oracle.afps(pts, c, m, k, start, lib=lib, flags=flags)
+            except oracle.OracleError:
+                return False
+            if got.tolist() != bruteforce.afps(pts, c, m, k, start, flags).tolist():
+                return False
     return True
 
 

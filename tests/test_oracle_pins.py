@@ -31,10 +31,11 @@ def _cases():
 @pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"])
 def test_hand_examples(case):
     pts = np.array(case["points"], dtype=np.float32)
-    got = oracle.afps(pts, case["c"], case["m"], case["k"], case["start"])
+    flags = case.get("flags", 0)
+    got = oracle.afps(pts, case["c"], case["m"], case["k"], case["start"], flags=flags)
     assert got.tolist() == case["expected"]
     # the brute force agrees with the hand derivation as well
-    bf = bruteforce.afps(pts, case["c"], case["m"], case["k"], case["start"])
+    bf = bruteforce.afps(pts, case["c"], case["m"], case["k"], case["start"], flags)
     assert bf.tolist() == case["expected"]
 
 
@@ -251,3 +252,84 @@ def test_argument_errors():
     for c, m, start in [(0, 1, 0), (5, 1, 0), (2, 3, 0), (2, 0, 0), (2, 1, 4), (2, 1, -1)]:
         with pytest.raises(oracle.OracleError):
             oracle.afps(pts, c, m, None, start)
+
+
+# ---------------------------------------------------------------- NPDU readings
+
+FF, SH, SELF = oracle.NPDU_FIRST_FULL, oracle.NPDU_SHIFT_EDGES, oracle.NPDU_K_WITH_SELF
+
+
+@pytest.mark.parametrize("flags", [FF, SH, SELF, FF | SH, FF | SELF, SH | SELF, FF | SH | SELF])
+def test_bruteforce_agreement_npdu_readings(flags):
+    """Every combination of the alternative NPDU readings equals the
+    recomputation from scratch (windows formulated independently there)."""
+    rng = np.random.default_rng(4321 + flags)
+    for kind in ("uniform", "grid", "sorted", "dups"):
+        for _ in range(25):
+            n = int(rng.integers(1, 48))
+            pts = _random_cloud(rng, n, kind)
+            c = int(rng.integers(1, n + 1))
+            m = int(rng.integers(1, c + 1))
+            k = [1, 2, 3, 4, 5, 8, 13, 2 * n][int(rng.integers(0, 8))]
+            start = int(rng.integers(0, n))
+            want = bruteforce.afps(pts, c, m, k, start, flags)
+            got = oracle.afps(pts, c, m, k, start, flags=flags)
+            assert got.tolist() == want.tolist(), (kind, n, c, m, k, start, flags)
+
+
+def test_k_with_self_is_the_default_window_one_smaller():
+    """k points counting the sample = floor((k-1)/2) below and ceil((k-1)/2)
+    above, which is the default window of k - 1 neighbours."""
+    rng = np.random.default_rng(8)
+    for _ in range(40):
+        n = int(rng.integers(2, 300))
+        pts = rng.random((n, 3), dtype=np.float32)
+        c = int(rng.integers(1, n + 1))
+        m = int(rng.integers(1, c + 1))
+        k = int(rng.integers(1, 70))
+        start = int(rng.integers(0, n))
+        for extra in (0, FF, SH):
+            assert oracle.afps(pts, c, m, k, start, flags=SELF | extra).tolist() == \
+                oracle.afps(pts, c, m, k - 1, start, flags=extra).tolist()
+
+
+def test_first_full_with_k0_picks_by_distance_from_start():
+    """After one full update from the start point and windows holding only the
+    sample, the picks are the points in decreasing order of their distance
+    from the start (ties to the lowest index)."""
+    rng = np.random.default_rng(9)
+    for n in (5, 17, 64, 200):
+        pts = rng.random((n, 3), dtype=np.float32)
+        start = int(rng.integers(0, n))
+        d = np.array([np.float32(np.float32(np.float32((p[0] - pts[start, 0]) ** 2) + np.float32((p[1] - pts[start, 1]) ** 2))
+                                 + np.float32((p[2] - pts[start, 2]) ** 2)) for p in pts], dtype=np.float32)
+        order = sorted(range(n), key=lambda j: (-float(d[j]), j))
+        got = oracle.afps(pts, n, 1, 0, start, flags=FF)
+        assert got.tolist() == [start] + order[:n - 1]
+
+
+def test_readings_coincide_when_the_window_spans_the_sector():
+    """k >= 2 n_s: every window covers the sector, so each reading is local FPS."""
+    rng = np.random.default_rng(10)
+    pts = rng.random((300, 3), dtype=np.float32)
+    for m in (1, 3, 7):
+        ref = oracle.afps(pts, 120, m, None, 11)
+        for flags in (0, FF, SH, FF | SH, SELF, FF | SH | SELF):
+            assert oracle.afps(pts, 120, m, 2 * 300 + 1, 11, flags=flags).tolist() == ref.tolist()
+
+
+def test_shift_matches_truncation_away_from_the_edges():
+    """With the start and every later window clear of both edges the two
+    readings update the same points; at k = 0 a window never crosses an edge."""
+    rng = np.random.default_rng(11)
+    pts = rng.random((200, 3), dtype=np.float32)
+    for start in (0, 57, 199):
+        assert oracle.afps(pts, 80, 2, 0, start, flags=SH).tolist() == \
+            oracle.afps(pts, 80, 2, 0, start).tolist()
+
+
+def test_reading_flags_are_checked():
+    pts = np.zeros((8, 3), np.float32)
+    for bad in [dict(k=None, flags=FF), dict(k=0, flags=SELF), dict(k=3, flags=8)]:
+        with pytest.raises(oracle.OracleError):
+            oracle.afps(pts, 4, 1, bad["k"], 0, flags=bad["flags"])
