@@ -85,23 +85,43 @@ int afps_afps(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t start,
 int afps_afps_npdu(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
                    int32_t start, int32_t *out_idx, void *stream);
 
+/*
+ * The readings of Sec. III-C that the paper leaves open, as alternatives to the
+ * ones afps_afps_npdu takes (bit flags, combinable):
+ *   AFPS_NPDU_FIRST_FULL : the first iteration updates every point of the
+ *                          sector from the start point; later ones the window;
+ *   AFPS_NPDU_SHIFT_EDGES: a window that would cross a sector edge is moved
+ *                          inward, keeping its k + 1 points where the sector
+ *                          allows, instead of being truncated;
+ *   AFPS_NPDU_K_WITH_SELF: the k updated points include the sample
+ *                          (floor((k-1)/2) below, ceil((k-1)/2) above); k >= 1.
+ */
+#define AFPS_NPDU_FIRST_FULL 1
+#define AFPS_NPDU_SHIFT_EDGES 2
+#define AFPS_NPDU_K_WITH_SELF 4
+
+/* afps_afps_npdu with reading flags (0 = afps_afps_npdu); AFPS_ERR_ARG for
+ * unknown bits, or K_WITH_SELF with k < 1. */
+int afps_afps_npdu_ex(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
+                      int32_t start, int32_t flags, int32_t *out_idx, void *stream);
+
 /* Largest sector (points) a single workgroup holds in registers. */
 int32_t afps_max_sector_points(void);
 
 /* ---------------------------------------------------------------- batches */
 
 /*
- * One cloud of a batch (ALG-5 of the paper's setting: many clouds per call,
- * here of uneven size).  xyz_offset counts points into xyz_all, out_offset
- * counts indices into out_all.  k < 0 turns NPDU off; m == 1 && k < 0 is plain
- * FPS.  Indices written are local to the cloud (0 .. n-1).
+ * One cloud of a batch (Table I's setting of many clouds per call, here of
+ * uneven size).  xyz_offset counts points into xyz_all, out_offset counts
+ * indices into out_all.  k < 0 turns NPDU off; m == 1 && k < 0 is plain FPS.
+ * Indices written are local to the cloud (0 .. n-1).
  */
 typedef struct afps_cloud_desc {
     int64_t xyz_offset;
     int64_t out_offset;
     int32_t n, c, m, k;
     int32_t start;
-    int32_t reserved;          /* must be 0 */
+    int32_t flags;             /* NPDU reading flags (AFPS_NPDU_*); 0 without NPDU */
 } afps_cloud_desc;
 
 typedef struct afps_plan afps_plan;
@@ -201,16 +221,19 @@ void afps_tune_reset(void);
  * that variant is not built or the sectors do not fit it.
  */
 int afps_afps_variant(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
-                      int32_t start, int32_t *out_idx, int32_t waves, int32_t slots,
-                      void *stream);
+                      int32_t start, int32_t flags, int32_t *out_idx, int32_t waves,
+                      int32_t slots, void *stream);
 
 /*
  * Wave budget of batch plans created afterwards, in waves per SIMD.  0 (the
- * default) = no budget: each persistent grid is as large as stays resident,
- * at most one workgroup per work item.  With a budget, each bucket gets the
- * fewest workgroups whose longest-first schedule of its estimated item costs
- * ends by the plan's longest item, raised until all grids together keep about
- * this many waves per SIMD.  Process-wide; AFPS_ERR_ARG outside [0, 64].
+ * default) = no budget: each persistent FPS/AFPS grid is as large as stays
+ * resident, at most one workgroup per work item, and the pooled NPDU launch
+ * picks one or two waves per SIMD from the plan's longest sector and total
+ * work.  With a budget, each FPS/AFPS bucket gets the fewest workgroups whose
+ * longest-first schedule of its estimated item costs ends by the plan's
+ * longest item, raised until all grids together keep about this many waves
+ * per SIMD, and the pooled NPDU launch runs one wave per SIMD below 1.5 and
+ * two from 1.5.  Process-wide; AFPS_ERR_ARG outside [0, 64].
  */
 int afps_set_plan_occupancy(float waves_per_simd);
 

@@ -27,7 +27,7 @@ class AfpsError(RuntimeError):
 class CloudDesc(ctypes.Structure):
     _fields_ = [("xyz_offset", ctypes.c_int64), ("out_offset", ctypes.c_int64),
                 ("n", ctypes.c_int32), ("c", ctypes.c_int32), ("m", ctypes.c_int32),
-                ("k", ctypes.c_int32), ("start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("k", ctypes.c_int32), ("start", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 def library_path() -> str:
@@ -54,7 +54,8 @@ def lib():
             "afps_fps_plain": ([vp, i32, i32, i32, vp, vp], ctypes.c_int),
             "afps_afps": ([vp, i32, i32, i32, i32, vp, vp], ctypes.c_int),
             "afps_afps_npdu": ([vp, i32, i32, i32, i32, i32, vp, vp], ctypes.c_int),
-            "afps_afps_variant": ([vp, i32, i32, i32, i32, i32, vp, i32, i32, vp], ctypes.c_int),
+            "afps_afps_npdu_ex": ([vp, i32, i32, i32, i32, i32, i32, vp, vp], ctypes.c_int),
+            "afps_afps_variant": ([vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, vp], ctypes.c_int),
             "afps_max_sector_points": ([], i32),
             "afps_plan_create": ([vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
             "afps_plan_workspace_bytes": ([vp], sz),
@@ -143,36 +144,43 @@ def afps(xyz, c: int, m: int, start: int = 0, out=None, stream=None, variant=Non
         rc = lib().afps_afps(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, start,
                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
     else:
-        rc = lib().afps_afps_variant(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, -1, start,
+        rc = lib().afps_afps_variant(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, -1, start, 0,
                                      ctypes.c_void_p(out.data_ptr()), variant[0], variant[1],
                                      _stream_handle(stream))
     _check(rc)
     return out
 
 
-def afps_npdu(xyz, c: int, m: int, k: int, start: int = 0, out=None, stream=None, variant=None):
-    """AFPS with NPDU window k (Sec. III-C) -> int32 indices, sector-major."""
+# NPDU readings other than the default (AFPS_NPDU_* in include/afps.h).
+NPDU_FIRST_FULL, NPDU_SHIFT_EDGES, NPDU_K_WITH_SELF = 1, 2, 4
+
+
+def afps_npdu(xyz, c: int, m: int, k: int, start: int = 0, out=None, stream=None, variant=None,
+              flags: int = 0):
+    """AFPS with NPDU window k (Sec. III-C) -> int32 indices, sector-major.
+    ``flags`` selects the alternative readings (NPDU_*)."""
     _check_points(xyz)
     out = _out(xyz, c, out)
     if variant is None:
-        rc = lib().afps_afps_npdu(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, k, start,
-                                  ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+        rc = lib().afps_afps_npdu_ex(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, k, start, flags,
+                                     ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
     else:
-        rc = lib().afps_afps_variant(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, k, start,
+        rc = lib().afps_afps_variant(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, k, start, flags,
                                      ctypes.c_void_p(out.data_ptr()), variant[0], variant[1],
                                      _stream_handle(stream))
     _check(rc)
     return out
 
 
-def descriptors(sizes, cs, ms, ks, starts):
+def descriptors(sizes, cs, ms, ks, starts, flags=None):
     """Host descriptor array for clouds packed back to back (points and outputs)."""
     n = len(sizes)
     arr = (CloudDesc * n)()
     xo = oo = 0
     for i in range(n):
         arr[i] = CloudDesc(xo, oo, int(sizes[i]), int(cs[i]), int(ms[i]),
-                           -1 if ks[i] is None else int(ks[i]), int(starts[i]), 0)
+                           -1 if ks[i] is None else int(ks[i]), int(starts[i]),
+                           0 if flags is None else int(flags[i]))
         xo += int(sizes[i])
         oo += int(cs[i])
     return arr, xo, oo
@@ -184,9 +192,9 @@ class BatchPlan:
     Owns the device workspace (a torch tensor) and the library's plan.
     """
 
-    def __init__(self, sizes, cs, ms, ks, starts, device="cuda"):
+    def __init__(self, sizes, cs, ms, ks, starts, device="cuda", flags=None):
         torch = _torch()
-        self.descs, self.total_points, self.total_samples = descriptors(sizes, cs, ms, ks, starts)
+        self.descs, self.total_points, self.total_samples = descriptors(sizes, cs, ms, ks, starts, flags)
         h = ctypes.c_void_p()
         _check(lib().afps_plan_create(ctypes.cast(self.descs, ctypes.c_void_p), len(sizes), ctypes.byref(h)))
         self._plan = h

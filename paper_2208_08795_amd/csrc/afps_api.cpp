@@ -231,6 +231,20 @@ int32_t largest_sector(int32_t n, int32_t m) { return n / m + (n % m ? 1 : 0); }
 // then spans the sector from any sample); clamping keeps index sums in range.
 int32_t clamp_k(int32_t k, int32_t n_s) { return k > 2 * n_s ? 2 * n_s : k; }
 
+// NPDU reading flags: checked, and k counting the sample turned into the same
+// window one smaller (the kernels implement the other two readings).
+int npdu_readings(int32_t* k, int32_t* flags) {
+    if (*flags & ~(AFPS_NPDU_FIRST_FULL | AFPS_NPDU_SHIFT_EDGES | AFPS_NPDU_K_WITH_SELF))
+        return fail(AFPS_ERR_ARG, "unknown NPDU reading flags");
+    if (*flags && *k < 0) return fail(AFPS_ERR_ARG, "NPDU reading flags need NPDU (k >= 0)");
+    if (*flags & AFPS_NPDU_K_WITH_SELF) {
+        if (*k < 1) return fail(AFPS_ERR_ARG, "k must be >= 1 when it counts the sample");
+        *k -= 1;
+        *flags &= ~AFPS_NPDU_K_WITH_SELF;
+    }
+    return AFPS_OK;
+}
+
 // ------------------------------------------------------------ launches
 
 int launch_full_direct(const VariantEntry& v, const float* xyz, int32_t n, int32_t c, int32_t m,
@@ -241,9 +255,10 @@ int launch_full_direct(const VariantEntry& v, const float* xyz, int32_t n, int32
 }
 
 int launch_npdu_direct(const NpduEntry& v, const float* xyz, int32_t n, int32_t c, int32_t m,
-                       int32_t k, int32_t start, int32_t* out, hipStream_t stream) {
+                       int32_t k, int32_t start, int32_t flags, int32_t* out, hipStream_t stream) {
     const int lds = npdu_lds_bytes(v, largest_sector(n, m));
-    void* args[] = {(void*)&xyz, (void*)&n, (void*)&c, (void*)&m, (void*)&k, (void*)&start, (void*)&out};
+    void* args[] = {(void*)&xyz, (void*)&n, (void*)&c, (void*)&m, (void*)&k, (void*)&start, (void*)&flags,
+                    (void*)&out};
     AFPS_HIP(hipLaunchKernel(v.direct, dim3(m), dim3(64), args, lds, stream));
     return AFPS_OK;
 }
@@ -431,12 +446,13 @@ int afps_afps(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t start, 
     return afps_impl(xyz, n, c, m, start, out_idx, stream);
 }
 
-int afps_afps_npdu(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
-                   int32_t* out_idx, void* stream) {
+int afps_afps_npdu_ex(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
+                      int32_t flags, int32_t* out_idx, void* stream) {
     if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
     int rc = check_sizes(n, c, m, start);
     if (rc) return rc;
     if (k < 0) return fail(AFPS_ERR_ARG, "NPDU needs k >= 0");
+    if ((rc = npdu_readings(&k, &flags))) return rc;
     const int32_t ns = largest_sector(n, m);
     const NpduEntry* v = choose_npdu(ns);
     if (!v)
@@ -445,7 +461,12 @@ int afps_afps_npdu(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k,
     if ((rc = maybe_check_cloud(xyz, n, stream))) return rc;
     DeviceState* d;
     if ((rc = device_state(&d))) return rc;
-    return launch_npdu_direct(*v, xyz, n, c, m, clamp_k(k, ns), start, out_idx, (hipStream_t)stream);
+    return launch_npdu_direct(*v, xyz, n, c, m, clamp_k(k, ns), start, flags, out_idx, (hipStream_t)stream);
+}
+
+int afps_afps_npdu(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
+                   int32_t* out_idx, void* stream) {
+    return afps_afps_npdu_ex(xyz, n, c, m, k, start, 0, out_idx, stream);
 }
 
 int afps_fps_plain(const float* xyz, int32_t n, int32_t c, int32_t start, int32_t* out_idx,
@@ -458,10 +479,11 @@ int afps_fps_plain(const float* xyz, int32_t n, int32_t c, int32_t start, int32_
 }
 
 int afps_afps_variant(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t k, int32_t start,
-                      int32_t* out_idx, int32_t waves, int32_t slots, void* stream) {
+                      int32_t flags, int32_t* out_idx, int32_t waves, int32_t slots, void* stream) {
     if (!xyz || !out_idx) return fail(AFPS_ERR_NULL, "xyz and out_idx must be non-null");
     int rc = check_sizes(n, c, m, start);
     if (rc) return rc;
+    if ((rc = npdu_readings(&k, &flags))) return rc;
     if ((rc = maybe_check_cloud(xyz, n, stream))) return rc;
     const int32_t ns = largest_sector(n, m);
     DeviceState* d;
@@ -470,7 +492,7 @@ int afps_afps_variant(const float* xyz, int32_t n, int32_t c, int32_t m, int32_t
         // NPDU: `slots` selects the chunk size in units of 64 points.
         for (const auto& v : registry().npdu)
             if (v.chunk64 == slots && capacity(v) >= ns && waves == 1)
-                return launch_npdu_direct(v, xyz, n, c, m, clamp_k(k, ns), start, out_idx,
+                return launch_npdu_direct(v, xyz, n, c, m, clamp_k(k, ns), start, flags, out_idx,
                                           (hipStream_t)stream);
         return fail(AFPS_ERR_UNSUPPORTED, "no such NPDU variant for this sector size");
     }
@@ -616,10 +638,11 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     for (int32_t b = 0; b < batch; ++b) {
         const afps_cloud_desc& d = descs[b];
         const std::string where = "descriptor " + std::to_string(b) + ": ";
-        if (d.reserved != 0 || d.xyz_offset < 0 || d.out_offset < 0)
-            return fail(AFPS_ERR_ARG, where + "negative offset or nonzero reserved field");
+        if (d.xyz_offset < 0 || d.out_offset < 0) return fail(AFPS_ERR_ARG, where + "negative offset");
         int rc = check_sizes(d.n, d.c, d.m, d.start);
         if (rc) return fail(rc, where + g_last_error);
+        int32_t dk = d.k, dflags = d.flags;
+        if ((rc = npdu_readings(&dk, &dflags))) return fail(rc, where + g_last_error);
         plan->clouds.push_back(CheckSeg{d.xyz_offset, d.n, 0});
         const int32_t qn = d.n / d.m, rn = d.n % d.m, qc = d.c / d.m, rc_ = d.c % d.m;
         for (int32_t s = 0; s < d.m; ++s) {
@@ -631,11 +654,11 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             it.out_offset = d.out_offset + os;
             it.n = ns;
             it.c = cs;
-            it.k = d.k < 0 ? -1 : clamp_k(d.k, ns);
+            it.k = dk < 0 ? -1 : clamp_k(dk, ns);
             it.start = d.start % ns;
             it.base = bs;
-            it.pad = 0;
-            if (d.k >= 0) {
+            it.flags = dflags;
+            if (dk >= 0) {
                 if (npdu_r_for(ns) == 0) return fail(AFPS_ERR_UNSUPPORTED, where + "NPDU sector too large");
                 st.kernel = nullptr;
                 st.pages = npdu_pool_pages(ns);

@@ -9,14 +9,14 @@ namespace afps {
 
 template <int R, bool XYZ>
 __global__ __launch_bounds__(64) void direct_npdu_kernel(const float* __restrict__ xyz, int n, int c,
-                                                         int m, int k, int start,
+                                                         int m, int k, int start, int flags,
                                                          int32_t* __restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) uint32_t dyn_lds[];
     const int s = blockIdx.x;
     const int qn = n / m, rn = n % m, qc = c / m, rc = c % m;
     const int ns = qn + (s < rn ? 1 : 0), b = s * qn + min(s, rn);
     const int cs = qc + (s < rc ? 1 : 0), o = s * qc + min(s, rc);
-    sample_sector_npdu<R, XYZ>(xyz + 3 * (int64_t)b, ns, cs, k, start % ns, b, out + o, dyn_lds);
+    sample_sector_npdu<R, XYZ>(xyz + 3 * (int64_t)b, ns, cs, k, start % ns, b, out + o, dyn_lds, flags);
 }
 
 template <int R, bool XYZ>

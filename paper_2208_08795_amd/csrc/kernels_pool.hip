@@ -61,10 +61,10 @@ __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int3
     const float* xyz = xyz_all + 3 * wi.xyz_offset;
     int32_t* out = out_all + wi.out_offset;
     switch (npdu_r_for(wi.n)) {
-        case 1: sample_sector_npdu<1, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
-        case 2: sample_sector_npdu<2, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
-        case 4: sample_sector_npdu<4, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
-        default: sample_sector_npdu<8, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds); break;
+        case 1: sample_sector_npdu<1, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
+        case 2: sample_sector_npdu<2, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
+        case 4: sample_sector_npdu<4, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
+        default: sample_sector_npdu<8, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
     }
 }
 

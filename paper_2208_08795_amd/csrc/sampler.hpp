@@ -350,9 +350,11 @@ __device__ __forceinline__ void sector_lds_ready() {
 //   5. the overall maximum is the larger of (2) and (4); the lowest lane
 //      holding it is the lowest block, whose first index is the next sample.
 // Ties therefore go to the lowest index, as in Algorithm 1.
+template <bool SHIFT>
 __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restrict__ xyz, int n, int c,
                                                           int k, int cur, int base,
-                                                          int32_t* __restrict__ out, uint32_t* lds) {
+                                                          int32_t* __restrict__ out, uint32_t* lds,
+                                                          bool first_full) {
     const int lane = threadIdx.x & 63;
     const int nb = (n + 63) >> 6;
     const int np = npdu_padded_points(n);
@@ -369,6 +371,14 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
         __builtin_memcpy(rec + 4 * j, &r, 16);
     };
     const uint32_t init = __float_as_uint(kInitialDistance);
+    // Full first update (kNpduFirstFull): the distances from the start point
+    // are taken while the sector loads.
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    if (first_full) {
+        fx = xyz[3 * cur];
+        fy = xyz[3 * cur + 1];
+        fz = xyz[3 * cur + 2];
+    }
 
     // Load in rounds of kLoadRound points per lane, every load of a round in
     // flight at once (the rounds are latency bound).  Indices past n read
@@ -385,7 +395,9 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
 #pragma unroll
         for (int u = 0; u < kLoadRound; ++u) {
             const int jj = j0 + 64 * u + lane;
-            if (jj < np) write(jj, jj < n ? init : 0u, v[3 * u], v[3 * u + 1], v[3 * u + 2]);
+            uint32_t d = jj < n ? init : 0u;
+            if (first_full && jj < n) d = min(init, sq_dist_bits(v[3 * u], v[3 * u + 1], v[3 * u + 2], fx, fy, fz));
+            if (jj < np) write(jj, d, v[3 * u], v[3 * u + 1], v[3 * u + 2]);
         }
     }
     sector_lds_ready();
@@ -398,13 +410,45 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     const int below = k >> 1, above = k - (k >> 1);
     uint32_t* const rec_lane = rec + 4 * lane;   // this lane's record in block 0
     uint32_t picks = (uint32_t)cur;               // sector-local pick of step s in lane s
+    int s_first = 1;                              // step 0 of the sector is its start
+    if (first_full) {
+        // Every block's maximum after the full update, then its argmax: the
+        // sector's pick of step 1.
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t d = rec_lane[256 * b];
+            const uint32_t g = wave_max(d);
+            bm = writelane(bm, g, b);
+            bi = writelane(bi, (uint32_t)__builtin_ctzll(ballot(d == g)), b);
+        }
+        if (c > 1) {
+            const uint32_t g = wave_max(bm);
+            const int wl = (int)__builtin_ctzll(ballot(bm == g));
+            cur = 64 * wl + (int)readlane(bi, wl);
+            picks = writelane(picks, (uint32_t)cur, 1);
+            s_first = 2;
+        }
+    }
 
     // One iteration of the loop: the new sample's record, the two blocks
     // holding its window, their update and re-reduction, the next sample.
     auto step = [&](int s) {
         const uint4 P = read(cur);
-        const int lo = max(0, cur - below);
-        const int hi = min(n - 1, cur + above);
+        int lo, hi;
+        if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
+            lo = cur - below;
+            hi = cur + above;
+            if (lo < 0) {
+                hi -= lo;
+                lo = 0;
+            }
+            if (hi > n - 1) {
+                lo = max(0, lo - (hi - (n - 1)));
+                hi = n - 1;
+            }
+        } else {
+            lo = max(0, cur - below);
+            hi = min(n - 1, cur + above);
+        }
         const int blo = lo >> 6;
         uint32_t* const wb = rec_lane + 256 * blo;   // this lane's record in block blo
         uint4 A, B;
@@ -451,7 +495,7 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     // the counter and branch work of every other step.
     for (int i0 = 0; i0 < c; i0 += 64) {
         const int s_end = min(64, c - i0);
-        int s = i0 == 0 ? 1 : 0;                  // step 0 of the sector is its start
+        int s = i0 == 0 ? s_first : 0;
         for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
             step(s);
             step(s + 1);
@@ -483,10 +527,14 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
 template <int R, bool XYZ_IN_LDS>
 __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz, int n, int c,
                                                    int k, int cur, int base,
-                                                   int32_t* __restrict__ out, uint32_t* lds) {
+                                                   int32_t* __restrict__ out, uint32_t* lds,
+                                                   int flags) {
+    const bool first_full = (flags & kNpduFirstFull) != 0;
+    const bool shift = (flags & kNpduShiftEdges) != 0;
     if constexpr (R == 1 && XYZ_IN_LDS) {
         if (k <= 64) {
-            sample_sector_npdu_narrow(xyz, n, c, k, cur, base, out, lds);
+            if (shift) sample_sector_npdu_narrow<true>(xyz, n, c, k, cur, base, out, lds, first_full);
+            else sample_sector_npdu_narrow<false>(xyz, n, c, k, cur, base, out, lds, first_full);
             return;
         }
     }
@@ -517,7 +565,23 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
             }
         }
     }
-    for (int j = lane; j < np; j += 64) sd[j] = j < n ? __float_as_uint(kInitialDistance) : 0u;
+    // D starts at 1e10, or (kNpduFirstFull) at the distance from the start
+    // point: the full update of the first iteration.
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    if (first_full) {
+        if constexpr (XYZ_IN_LDS) { fx = sx[cur]; fy = sy[cur]; fz = sz[cur]; }
+        else { fx = xyz[3 * cur]; fy = xyz[3 * cur + 1]; fz = xyz[3 * cur + 2]; }
+    }
+    for (int j = lane; j < np; j += 64) {
+        uint32_t d = j < n ? __float_as_uint(kInitialDistance) : 0u;
+        if (first_full && j < n) {
+            float x, y, z;
+            if constexpr (XYZ_IN_LDS) { x = sx[j]; y = sy[j]; z = sz[j]; }
+            else { x = xyz[3 * j]; y = xyz[3 * j + 1]; z = xyz[3 * j + 2]; }
+            d = min(d, sq_dist_bits(x, y, z, fx, fy, fz));
+        }
+        sd[j] = d;
+    }
     sector_lds_ready();
 
     uint32_t bm[R], bi[R];
@@ -531,10 +595,51 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
     // Picks are buffered one per lane (pick i in lane i mod 64) and written
     // 64 at a time.
     uint32_t picks = (uint32_t)(base + cur);
+    int i_first = 1;
+    if (first_full) {
+        // Every block's maximum and its lowest index after the full update,
+        // then the pick of iteration 1.
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            for (int l = 0; l < 64 && 64 * r + l < nb; ++l) {
+                const int blk = 64 * r + l;
+                const uint32_t d = sd[64 * blk + lane];
+                const uint32_t g = wave_max(d);
+                bm[r] = writelane(bm[r], g, l);
+                bi[r] = writelane(bi[r], (uint32_t)(64 * blk) + (uint32_t)__builtin_ctzll(ballot(d == g)), l);
+            }
+        }
+        if (c > 1) {
+            uint32_t mx = 0u;
+#pragma unroll
+            for (int r = 0; r < R; ++r) mx = max(mx, bm[r]);
+            const uint32_t g = wave_max(mx);
+            int pick = -1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t hit = ballot(bm[r] == g);
+                if (pick < 0 && hit) pick = (int)readlane(bi[r], (int)__builtin_ctzll(hit));
+            }
+            cur = pick;
+            picks = lane == 1 ? (uint32_t)(base + cur) : picks;
+            i_first = 2;
+        }
+    }
 
-    for (int i = 1; i < c; ++i) {
-        const int lo = max(0, cur - below);
-        const int hi = min(n - 1, cur + above);
+    for (int i = i_first; i < c; ++i) {
+        int lo = cur - below, hi = cur + above;
+        if (shift) {   // kNpduShiftEdges: keep the window's size inside the sector
+            if (lo < 0) {
+                hi -= lo;
+                lo = 0;
+            }
+            if (hi > n - 1) {
+                lo -= hi - (n - 1);
+                hi = n - 1;
+            }
+        }
+        lo = max(0, lo);
+        hi = min(n - 1, hi);
         const int blo = lo >> 6, bhi = hi >> 6;
         const uint32_t span = (uint32_t)(hi - lo);
 

@@ -8,6 +8,18 @@
 
 namespace afps {
 
+// NPDU readings other than the default one, for points Sec. III-C leaves open
+// (bit flags of the NPDU entry points and of a work item):
+//   kNpduFirstFull : the first iteration updates every point of the sector;
+//   kNpduShiftEdges: a window that would cross a sector edge is moved inward
+//                    (keeping its size) instead of being truncated;
+//   kNpduKWithSelf : the k updated points include the sample; the host turns
+//                    it into k - 1 without the flag (the same window), so the
+//                    kernels never see it.
+constexpr int kNpduFirstFull = 1;
+constexpr int kNpduShiftEdges = 2;
+constexpr int kNpduKWithSelf = 4;
+
 // One sector's work, as the batch queue hands it out (40 bytes).
 struct WorkItem {
     int64_t xyz_offset;   // first point of the sector, in points, into xyz_all
@@ -17,7 +29,7 @@ struct WorkItem {
     int32_t k;            // NPDU window parameter, < 0 = off
     int32_t start;        // local start point (start mod n)
     int32_t base;         // index of the sector's first point inside its cloud
-    int32_t pad;
+    int32_t flags;        // NPDU readings (kNpdu* below), 0 without NPDU
 };
 static_assert(sizeof(WorkItem) == 40, "work item layout");
 

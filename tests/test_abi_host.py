@@ -57,6 +57,14 @@ def test_host_validation_without_gpu(L):
     assert L.afps_check_points(dummy, -1, None) == -2
     assert L.afps_check_points(dummy, 0, None) == 0          # empty cloud: nothing to read
     assert L.afps_set_checking(0) == 0
+    # NPDU reading flags: unknown bits, k counting the sample with k = 0
+    assert L.afps_afps_npdu_ex(dummy, 10, 5, 1, 3, 0, 8, dummy, None) == -2
+    assert L.afps_afps_npdu_ex(dummy, 10, 5, 1, 0, 0, 4, dummy, None) == -2
+    assert "counts the sample" in L.afps_last_error().decode()
+    fl, _, _ = binding.descriptors([100, 50], [10, 20], [2, 1], [4, None], [0, 0], flags=[1, 2])
+    fplan = ctypes.c_void_p()
+    assert L.afps_plan_create(ctypes.cast(fl, ctypes.c_void_p), 2, ctypes.byref(fplan)) == -2
+    assert "descriptor 1" in L.afps_last_error().decode()
     # bad descriptors are rejected before any device work
     descs, _, _ = binding.descriptors([100, 50], [10, 60], [2, 1], [None, 4], [0, 0])
     plan = ctypes.c_void_p()

@@ -33,23 +33,23 @@ def B():
     return binding
 
 
-def _run(B, torch, xyz_t, c, m, k, start, variant=None):
+def _run(B, torch, xyz_t, c, m, k, start, variant=None, flags=0):
     if k is None and m == 1 and variant is None:
         out = B.fps(xyz_t, c, start)
     elif k is None:
         out = B.afps(xyz_t, c, m, start, variant=variant)
     else:
-        out = B.afps_npdu(xyz_t, c, m, k, start, variant=variant)
+        out = B.afps_npdu(xyz_t, c, m, k, start, variant=variant, flags=flags)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
 
-def _check(B, torch, dev, pts, c, m, k, start, variant=None, label=""):
-    print("case %s n=%d c=%d m=%d k=%s start=%d variant=%s" % (label, len(pts), c, m, k, start, variant),
-          flush=True)
+def _check(B, torch, dev, pts, c, m, k, start, variant=None, label="", flags=0):
+    print("case %s n=%d c=%d m=%d k=%s start=%d variant=%s flags=%d" % (label, len(pts), c, m, k, start,
+                                                                       variant, flags), flush=True)
     xyz = torch.from_numpy(np.ascontiguousarray(pts, dtype=np.float32)).to(dev)
-    got = _run(B, torch, xyz, c, m, k, start, variant)
-    want = oracle.afps(pts, c, m, k, start)
+    got = _run(B, torch, xyz, c, m, k, start, variant, flags)
+    want = oracle.afps(pts, c, m, k, start, flags=flags)
     if not np.array_equal(got, want):
         bad = np.flatnonzero(got != want)
         raise AssertionError("%s: %d mismatches, first at %d: got %d want %d" %
@@ -62,7 +62,7 @@ def test_hand_examples(B, torch_dev):
         for case in json.load(f)["cases"]:
             pts = np.array(case["points"], dtype=np.float32)
             xyz = torch.from_numpy(pts).to(dev)
-            got = _run(B, torch, xyz, case["c"], case["m"], case["k"], case["start"])
+            got = _run(B, torch, xyz, case["c"], case["m"], case["k"], case["start"], flags=case.get("flags", 0))
             assert got.tolist() == case["expected"], case["name"]
 
 
@@ -152,6 +152,59 @@ def test_npdu_narrow_window_edges(B, torch_dev):
             _check(B, torch, dev, pts, n, 1, k, n - 1, label="narrow-small")
 
 
+READING_FLAGS = (1, 2, 3, 4, 5, 6, 7)   # full first update, shifted windows, k counting the sample
+
+
+def test_npdu_readings_random(B, torch_dev):
+    """The alternative NPDU readings on random clouds: both window paths
+    (k <= 64 and wider), ragged sectors, every flag combination."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(606)
+    for it in range(70):
+        n = int(rng.integers(1, 6000))
+        pts = synth.object_cloud(n, int(rng.integers(0, 1 << 30))) if it % 2 else rng.random((n, 3), dtype=np.float32)
+        c = int(rng.integers(1, min(n, 600) + 1))
+        m = int(rng.integers(1, min(c, 24) + 1))
+        k = [1, 2, 7, 32, 63, 64, 65, 129, 3 * n][int(rng.integers(0, 9))]
+        flags = READING_FLAGS[it % len(READING_FLAGS)]
+        start = int(rng.integers(0, n))
+        _check(B, torch, dev, pts, c, m, k, start, label="readings-%d" % it, flags=flags)
+
+
+@pytest.mark.parametrize("q", [1, 2, 4, 8])
+def test_npdu_readings_every_variant(B, torch_dev, q):
+    torch, dev = torch_dev
+    n = 4096 * q - 101
+    pts = synth.object_cloud(n, seed=40 + q)
+    for k, flags, start in [(8, 1, 0), (64, 2, n - 1), (33, 3, 17), (200, 7, n // 2), (64, 4, 5)]:
+        _check(B, torch, dev, pts, min(n // 4, 1500), 1, k, start, variant=(1, q), label="readings-q%d" % q,
+               flags=flags)
+
+
+def test_npdu_readings_edges(B, torch_dev):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(607)
+    full = synth.object_cloud(4096, seed=12)
+    for c, k, flags, start in [(1, 5, 1, 9), (2, 5, 1, 9), (4096, 64, 2, 4095), (3000, 63, 3, 4000),
+                               (2000, 64, 6, 0), (4096, 2, 7, 2048)]:
+        _check(B, torch, dev, full, c, 1, k, start, variant=(1, 1), label="readings-4096", flags=flags)
+    one = rng.random((1, 3), dtype=np.float32)
+    for flags in READING_FLAGS:
+        _check(B, torch, dev, one, 1, 1, 3, 0, label="readings-one", flags=flags)
+    pts = rng.random((300, 3), dtype=np.float32)
+    for flags in READING_FLAGS:
+        _check(B, torch, dev, pts, 300, 7, 1000, 250, label="readings-wide", flags=flags)
+
+
+def test_npdu_readings_batched(B, torch_dev):
+    torch, dev = torch_dev
+    clouds = synth.batch_of_objects(40, seed=21, n_min=1024, n_max=32768)
+    cs = [len(p) // 4 for p in clouds]
+    _batch_case(B, torch, dev, clouds, cs, [8] * len(clouds), [32 if i % 3 else 64 for i in range(len(clouds))],
+                [i % 5 for i in range(len(clouds))], graph_replays=2,
+                flags=[((0,) + READING_FLAGS)[i % 8] for i in range(len(clouds))])
+
+
 def test_config1_plain_fps(B, torch_dev):
     torch, dev = torch_dev
     pts = synth.uniform_cube(2048, 0)
@@ -182,18 +235,18 @@ def test_grid_fps_large_clouds(B, torch_dev, n, c):
     _check(B, torch, dev, pts, c, 1, None, n // 7, label="grid-fps")
 
 
-def _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=0):
+def _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=0, flags=None):
     sizes = [len(p) for p in clouds]
-    print("batch clouds=%d points=%d ks=%s graph=%d" % (len(clouds), sum(sizes), sorted(set(map(str, ks))),
-                                                      graph_replays), flush=True)
-    plan = B.BatchPlan(sizes, cs, ms, ks, starts, device=dev)
+    print("batch clouds=%d points=%d ks=%s graph=%d flags=%s" % (len(clouds), sum(sizes), sorted(set(map(str, ks))),
+                                                               graph_replays, flags is not None), flush=True)
+    plan = B.BatchPlan(sizes, cs, ms, ks, starts, device=dev, flags=flags)
     xyz_all = torch.from_numpy(np.concatenate(clouds).astype(np.float32)).to(dev)
     out = plan.launch(xyz_all)
     torch.cuda.synchronize()
     eager = out.cpu().numpy().copy()
     for i, p in enumerate(clouds):
         o = plan.descs[i].out_offset
-        want = oracle.afps(p, cs[i], ms[i], ks[i], starts[i])
+        want = oracle.afps(p, cs[i], ms[i], ks[i], starts[i], flags=0 if flags is None else flags[i])
         assert np.array_equal(eager[o:o + cs[i]], want), "cloud %d" % i
     for r in range(graph_replays):
         out.fill_(-7)
