@@ -101,12 +101,12 @@ def single_cloud_latency(torch, binding, synth, stream, reps=20):
     """Single-frame latencies of the paper-sized configurations (ms, median of reps)."""
     res = {}
     cases = {
-        "cfg1_fps_n2048_c512": (synth.uniform_cube(2048, 0), dict(kind="fps", c=512)),
-        "cfg3_fps_n32768_c8192": (synth.lidar_scan(512, 0), dict(kind="fps", c=8192)),
-        "cfg3_afps_npdu_m16_k64": (synth.lidar_scan(512, 0), dict(kind="npdu", c=8192, m=16, k=64)),
-        "cfg2_afps_m32_n8192_c2048": (synth.object_cloud(8192, 0), dict(kind="afps", c=2048, m=32)),
-        "cfg2_afps_npdu_m32_k32": (synth.object_cloud(8192, 0), dict(kind="npdu", c=2048, m=32, k=32)),
-        "cfg2_fps_n8192_c2048": (synth.object_cloud(8192, 0), dict(kind="fps", c=2048)),
+        "cube_n2048_c512_fps": (synth.uniform_cube(2048, 0), dict(kind="fps", c=512)),
+        "lidar_n32768_c8192_fps": (synth.lidar_scan(512, 0), dict(kind="fps", c=8192)),
+        "lidar_n32768_c8192_npdu_m16_k64": (synth.lidar_scan(512, 0), dict(kind="npdu", c=8192, m=16, k=64)),
+        "object_n8192_c2048_afps_m32": (synth.object_cloud(8192, 0), dict(kind="afps", c=2048, m=32)),
+        "object_n8192_c2048_npdu_m32_k32": (synth.object_cloud(8192, 0), dict(kind="npdu", c=2048, m=32, k=32)),
+        "object_n8192_c2048_fps": (synth.object_cloud(8192, 0), dict(kind="fps", c=2048)),
     }
     for name, (pts, p) in cases.items():
         xyz = torch.from_numpy(pts).cuda()
@@ -123,7 +123,7 @@ def single_cloud_latency(torch, binding, synth, stream, reps=20):
             run()
         torch.cuda.synchronize()
         ts = []
-        r = reps if "32768_c8192" not in name else 3
+        r = reps if not name.endswith("n32768_c8192_fps") else 3
         for _ in range(r):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
@@ -139,10 +139,25 @@ def single_cloud_latency(torch, binding, synth, stream, reps=20):
 CLOCK_GHZ = 2.4   # MI355X peak engine clock (SQ counters measured 2.41 GHz under these kernels)
 
 
-def config2_sweep(torch, binding, synth, stream, reps=10):
+def _median_ms(torch, run, stream, reps):
+    run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run()
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def object_sweep(torch, binding, synth, stream, reps=10):
     """Object cloud N=8192, C=2048: plain FPS, AFPS for M in {1..32}, NPDU at
     k in {8, 32, 128}: time per call (median), cycles per iteration of the
-    longest sector, coverage radius relative to plain FPS."""
+    longest sector, coverage radius relative to plain FPS.  Then the
+    alternative NPDU readings at k in {8, 32}, M in {1, 8}."""
     from paper_2208_08795_amd.quality import coverage_radius
     pts = synth.object_cloud(8192, 0)
     xyz = torch.from_numpy(pts).cuda()
@@ -156,17 +171,7 @@ def config2_sweep(torch, binding, synth, stream, reps=10):
                     binding.afps(xyz, 2048, m, 0, out=out, stream=stream)
                 else:
                     binding.afps_npdu(xyz, 2048, m, k, 0, out=out, stream=stream)
-            run()
-            torch.cuda.synchronize()
-            ts = []
-            for _ in range(reps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                run()
-                b.record(stream)
-                b.synchronize()
-                ts.append(a.elapsed_time(b))
-            ms = float(np.median(ts))
+            ms = _median_ms(torch, run, stream, reps)
             r = coverage_radius(pts, out.cpu().numpy())
             if m == 1 and k is None:
                 ref = r
@@ -174,9 +179,24 @@ def config2_sweep(torch, binding, synth, stream, reps=10):
             rows.append({"m": m, "k": k, "ms": round(ms, 4), "sampled_pts_per_s": 2048 / (ms / 1e3),
                          "cycles_per_iteration": round(ms * 1e-3 * CLOCK_GHZ * 1e9 / iters, 1),
                          "coverage_radius": round(r, 5), "coverage_vs_fps": round(r / ref, 4)})
-    log("config-2 sweep: " + ", ".join("M%d/k%s %.3fms r%.2f" % (x["m"], x["k"], x["ms"], x["coverage_vs_fps"])
-                                       for x in rows))
-    return rows
+    log("object sweep: " + ", ".join("M%d/k%s %.3fms r%.2f" % (x["m"], x["k"], x["ms"], x["coverage_vs_fps"])
+                                     for x in rows))
+    names = {0: "default", binding.NPDU_FIRST_FULL: "first_full", binding.NPDU_SHIFT_EDGES: "shift_edges",
+             binding.NPDU_K_WITH_SELF: "k_with_self",
+             binding.NPDU_FIRST_FULL | binding.NPDU_SHIFT_EDGES: "first_full+shift_edges"}
+    readings = []
+    for m in (1, 8):
+        for k in (8, 32):
+            for flags, name in names.items():
+                def run():
+                    binding.afps_npdu(xyz, 2048, m, k, 0, out=out, stream=stream, flags=flags)
+                ms = _median_ms(torch, run, stream, reps)
+                r = coverage_radius(pts, out.cpu().numpy())
+                readings.append({"m": m, "k": k, "reading": name, "ms": round(ms, 4),
+                                 "coverage_radius": round(r, 5), "coverage_vs_fps": round(r / ref, 4)})
+    log("NPDU readings: " + ", ".join("M%d/k%d/%s %.3fms r%.2f" % (x["m"], x["k"], x["reading"], x["ms"],
+                                                                   x["coverage_vs_fps"]) for x in readings))
+    return rows, readings
 
 
 def serving(torch, rates=(50, 200, 800), frames_npdu=160, frames_fps=24, pool=48, seed=1):
@@ -386,11 +406,12 @@ def main():
     if not args.no_single:
         single = single_cloud_latency(torch, binding, synth, stream)
         res["single_cloud_ms"] = single
-        iters = {"cfg1_fps_n2048_c512": 511, "cfg3_fps_n32768_c8192": 8191, "cfg3_afps_npdu_m16_k64": 511,
-                 "cfg2_afps_m32_n8192_c2048": 63, "cfg2_afps_npdu_m32_k32": 63, "cfg2_fps_n8192_c2048": 2047}
+        iters = {"cube_n2048_c512_fps": 511, "lidar_n32768_c8192_fps": 8191, "lidar_n32768_c8192_npdu_m16_k64": 511,
+                 "object_n8192_c2048_afps_m32": 63, "object_n8192_c2048_npdu_m32_k32": 63,
+                 "object_n8192_c2048_fps": 2047}
         res["cycles_per_iteration"] = {k: round(v * 1e-3 * CLOCK_GHZ * 1e9 / iters[k], 1) for k, v in single.items()}
         res["cycles_per_iteration"]["note"] = "call time x 2.4 GHz / iterations of the longest sector (launch included)"
-        res["config2_sweep"] = config2_sweep(torch, binding, synth, stream)
+        res["object_n8192_c2048_sweep"], res["npdu_readings"] = object_sweep(torch, binding, synth, stream)
 
     if not args.no_serve:
         res["serving"] = serving(torch)

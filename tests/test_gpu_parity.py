@@ -205,27 +205,27 @@ def test_npdu_readings_batched(B, torch_dev):
                 flags=[((0,) + READING_FLAGS)[i % 8] for i in range(len(clouds))])
 
 
-def test_config1_plain_fps(B, torch_dev):
+def test_cube_2048_plain_fps(B, torch_dev):
     torch, dev = torch_dev
     pts = synth.uniform_cube(2048, 0)
-    _check(B, torch, dev, pts, 512, 1, None, 0, label="cfg1-fps")
-    _check(B, torch, dev, pts, 512, 1, None, 0, variant=(4, 8), label="cfg1-afps-m1")
+    _check(B, torch, dev, pts, 512, 1, None, 0, label="cube-fps")
+    _check(B, torch, dev, pts, 512, 1, None, 0, variant=(4, 8), label="cube-afps-m1")
 
 
-def test_config2_sweep(B, torch_dev):
+def test_object_8192_sweep(B, torch_dev):
     torch, dev = torch_dev
     pts = synth.object_cloud(8192, 0)
     for m in (1, 2, 4, 8, 16, 32):
         for k in (None, 8, 32, 128):
-            _check(B, torch, dev, pts, 2048, m, k, 0, label="cfg2")
+            _check(B, torch, dev, pts, 2048, m, k, 0, label="object-8192")
 
 
-def test_config3_lidar(B, torch_dev):
+def test_lidar_32768(B, torch_dev):
     torch, dev = torch_dev
     pts = synth.lidar_scan(512, 0)
-    _check(B, torch, dev, pts, 8192, 16, 64, 0, label="cfg3-npdu")
-    _check(B, torch, dev, pts, 8192, 16, None, 0, label="cfg3-afps")
-    _check(B, torch, dev, pts, 8192, 1, None, 0, label="cfg3-fps")
+    _check(B, torch, dev, pts, 8192, 16, 64, 0, label="lidar-npdu")
+    _check(B, torch, dev, pts, 8192, 16, None, 0, label="lidar-afps")
+    _check(B, torch, dev, pts, 8192, 1, None, 0, label="lidar-fps")
 
 
 @pytest.mark.parametrize("n,c", [(40000, 600), (131072, 1024), (70001, 3000)])
