@@ -244,6 +244,28 @@ int afps_set_plan_occupancy(float waves_per_simd);
  */
 int afps_set_spin_limit(uint32_t polls);
 
+/* ---------------------------------------------------------------- binning */
+
+/*
+ * Binning along one axis, Sec. III-A: a cloud without dimensional locality is
+ * binned instead of sorted, into the approximate order of the footnote to
+ * Table II (every point of a later bin has a larger coordinate; points inside
+ * a bin keep their storage order), which AFPS and NPDU then exploit.  With
+ * lo, hi the smallest and largest coordinate along `axis` (0 = x, 1 = y,
+ * 2 = z), each point goes to bin min(bins-1, floor((x - lo) * scale)),
+ * scale = bins / (hi - lo) in fp32 (0 when hi == lo).
+ *   perm     DEVICE, n int32: perm[i] = storage index of the i-th point in
+ *            binned order (a stable counting sort by bin)
+ *   xyz_out  DEVICE, n x 3 fp32 or NULL: the points in binned order (must
+ *            not be xyz)
+ *   workspace DEVICE, >= afps_bin_workspace_bytes(n, bins), 256-byte aligned
+ * Requires n >= 1 and 1 <= bins <= 8192.  Kernel launches only (a caller may
+ * capture them in a hipGraph); asynchronous on `stream`.
+ */
+size_t afps_bin_workspace_bytes(int32_t n, int32_t bins);   /* 0 if the sizes are invalid */
+int afps_bin_points(const float *xyz, int32_t n, int32_t axis, int32_t bins, int32_t *perm,
+                    float *xyz_out, void *workspace, size_t workspace_bytes, void *stream);
+
 /*
  * Input check of the preconditions above for one cloud of n points (DEVICE
  * xyz): every coordinate finite, and the squared diagonal of the bounding box

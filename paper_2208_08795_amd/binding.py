@@ -74,6 +74,8 @@ def lib():
             "afps_tune_reset": ([], None),
             "afps_set_spin_limit": ([ctypes.c_uint32], ctypes.c_int),
             "afps_check_points": ([vp, ctypes.c_int64, vp], ctypes.c_int),
+            "afps_bin_workspace_bytes": ([i32, i32], ctypes.c_size_t),
+            "afps_bin_points": ([vp, i32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
             "afps_set_checking": ([i32], ctypes.c_int),
             "afps_set_plan_occupancy": ([ctypes.c_float], ctypes.c_int),
             "afps_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -276,6 +278,22 @@ def check_points(xyz, stream=None):
     diagonal is not below 1e10."""
     _check_points(xyz)
     _check(lib().afps_check_points(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], _stream_handle(stream)))
+
+
+def bin_points(xyz, axis: int, bins: int, with_points: bool = True, stream=None):
+    """Binning along one axis (Sec. III-A): returns (perm, binned points or
+    None); perm[i] is the storage index of the i-th point in binned order."""
+    torch = _torch()
+    _check_points(xyz)
+    n = xyz.shape[0]
+    need = int(lib().afps_bin_workspace_bytes(n, bins))
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=xyz.device)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=xyz.device)
+    out = torch.empty_like(xyz) if with_points else None
+    _check(lib().afps_bin_points(ctypes.c_void_p(xyz.data_ptr()), n, axis, bins, ctypes.c_void_p(perm.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()) if out is not None else None,
+                                 ctypes.c_void_p(ws.data_ptr()), need, _stream_handle(stream)))
+    return perm[:n], out
 
 
 def set_checking(on: bool):

@@ -28,6 +28,7 @@ def _units():
     units = [("kernels.hip", "kernels_w%d.o" % w, ["-DAFPS_WAVES=%d" % w]) for w in (1, 2, 4, 8, 16)]
     units += [("kernels_npdu.hip", "kernels_npdu.o", []), ("kernels_pool.hip", "kernels_pool.o", []),
               ("fps_grid.hip", "fps_grid.o", []), ("check.hip", "check.o", []),
+              ("binning.hip", "binning.o", []),
               ("afps_api.cpp", "afps_api.o", ["-x", "hip"])]
     return units
 

@@ -547,6 +547,43 @@ int afps_set_plan_occupancy(float waves_per_simd) {
     return AFPS_OK;
 }
 
+size_t afps_bin_workspace_bytes(int32_t n, int32_t bins) {
+    if (n < 1 || bins < 1 || bins > kMaxBins) return 0;
+    const size_t chunks = ((size_t)n + kBinChunk - 1) / kBinChunk;
+    return sizeof(BinHeader) + (chunks * (size_t)bins * sizeof(uint32_t) + 255) / 256 * 256;
+}
+
+int afps_bin_points(const float* xyz, int32_t n, int32_t axis, int32_t bins, int32_t* perm, float* xyz_out,
+                    void* workspace, size_t workspace_bytes, void* stream_) {
+    if (!xyz || !perm) return fail(AFPS_ERR_NULL, "xyz and perm must be non-null");
+    if (n < 1) return fail(AFPS_ERR_ARG, "n must be >= 1");
+    if (axis < 0 || axis > 2) return fail(AFPS_ERR_ARG, "axis must be 0, 1 or 2");
+    if (bins < 1 || bins > kMaxBins) return fail(AFPS_ERR_ARG, "bins must be in [1, " + std::to_string(kMaxBins) + "]");
+    if (xyz_out == xyz) return fail(AFPS_ERR_ARG, "xyz_out must not be xyz");
+    const size_t need = afps_bin_workspace_bytes(n, bins);
+    if (!workspace || workspace_bytes < need)
+        return fail(AFPS_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace & 255) != 0) return fail(AFPS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    int rc = maybe_check_cloud(xyz, n, stream_);
+    if (rc) return rc;
+    hipStream_t stream = (hipStream_t)stream_;
+    const BinKernels k = bin_kernels();
+    BinHeader* h = (BinHeader*)workspace;
+    uint32_t* hist = (uint32_t*)((char*)workspace + sizeof(BinHeader));
+    int chunks = (int)(((int64_t)n + kBinChunk - 1) / kBinChunk);
+    void* a0[] = {&h};
+    AFPS_HIP(hipLaunchKernel(k.reset, dim3(1), dim3(64), a0, 0, stream));
+    void* a1[] = {(void*)&xyz, &n, &axis, &h};
+    AFPS_HIP(hipLaunchKernel(k.range, dim3(std::min(chunks, 1024)), dim3(256), a1, 0, stream));
+    void* a2[] = {(void*)&xyz, &n, &axis, &bins, &h, &hist};
+    AFPS_HIP(hipLaunchKernel(k.count, dim3(chunks), dim3(256), a2, 0, stream));
+    void* a3[] = {&hist, &chunks, &bins};
+    AFPS_HIP(hipLaunchKernel(k.scan, dim3(1), dim3(1024), a3, 0, stream));
+    void* a4[] = {(void*)&xyz, &n, &axis, &bins, &h, &hist, &perm, &xyz_out};
+    AFPS_HIP(hipLaunchKernel(k.scatter, dim3(chunks), dim3(64), a4, 0, stream));
+    return AFPS_OK;
+}
+
 int afps_check_points(const float* xyz, int64_t n, void* stream) {
     if (!xyz) return fail(AFPS_ERR_NULL, "xyz must be non-null");
     if (n < 0 || n > INT32_MAX) return fail(AFPS_ERR_ARG, "n must be in [0, 2^31-1]");

@@ -113,6 +113,19 @@ struct CheckResult {
 static_assert(sizeof(CheckResult) == 32, "check result layout");
 const void* check_points_kernel();
 
+// Binning along one axis (binning.hip): a stable counting sort by bin.
+constexpr int kBinChunk = 4096;   // points per histogram chunk (one scatter wave each)
+constexpr int kMaxBins = 8192;    // bins counted in LDS
+struct BinHeader {
+    uint32_t lo_key, hi_key;      // order keys of the smallest and largest coordinate
+    uint32_t pad[62];
+};
+static_assert(sizeof(BinHeader) == 256, "binning header");
+struct BinKernels {
+    const void *reset, *range, *count, *scan, *scatter;
+};
+BinKernels bin_kernels();
+
 // Multi-workgroup plain FPS (fps_grid.hip).
 struct GridVariant {
     int waves, slots;

@@ -57,6 +57,15 @@ def test_host_validation_without_gpu(L):
     assert L.afps_check_points(dummy, -1, None) == -2
     assert L.afps_check_points(dummy, 0, None) == 0          # empty cloud: nothing to read
     assert L.afps_set_checking(0) == 0
+    # binning: sizes and arguments checked on the host
+    assert L.afps_bin_workspace_bytes(0, 16) == 0 and L.afps_bin_workspace_bytes(10, 0) == 0
+    assert L.afps_bin_workspace_bytes(10, 8193) == 0
+    assert L.afps_bin_workspace_bytes(8192, 1024) == 256 + 2 * 1024 * 4
+    assert L.afps_bin_points(None, 10, 0, 4, dummy, None, dummy, 1 << 20, None) == -1
+    assert L.afps_bin_points(dummy, 10, 3, 4, dummy, None, dummy, 1 << 20, None) == -2
+    assert L.afps_bin_points(dummy, 10, 0, 9000, dummy, None, dummy, 1 << 20, None) == -2
+    assert L.afps_bin_points(dummy, 10, 0, 4, dummy, dummy, dummy, 1 << 20, None) == -2   # xyz_out == xyz
+    assert L.afps_bin_points(dummy, 10, 0, 4, dummy, None, dummy, 100, None) == -4
     # NPDU reading flags: unknown bits, k counting the sample with k = 0
     assert L.afps_afps_npdu_ex(dummy, 10, 5, 1, 3, 0, 8, dummy, None) == -2
     assert L.afps_afps_npdu_ex(dummy, 10, 5, 1, 0, 0, 4, dummy, None) == -2
