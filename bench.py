@@ -199,6 +199,50 @@ def object_sweep(torch, binding, synth, stream, reps=10):
     return rows, readings
 
 
+def sortedness(torch, binding, synth, stream, reps=10):
+    """Coverage radius of AFPS relative to plain FPS on the same points stored
+    in different orders (the paper's Table II setting, with the coverage radius
+    standing in for task accuracy): unsorted, approximately sorted along x
+    (bins of 128 points by rank), exactly sorted along x and along z, and
+    unsorted then binned on the GPU along x (N/128 value bins).  Plus the
+    binning's time at two sizes."""
+    from paper_2208_08795_amd.quality import coverage_radius
+    rng = np.random.default_rng(7)
+    base = synth.object_cloud(8192, 2)
+    unsorted = base[rng.permutation(len(base))]
+    orders = {"unsorted": unsorted,
+              "approx_sorted_x_bin128": synth.approx_sort(unsorted, unsorted[:, 0], 128, 3),
+              "sorted_x": synth.approx_sort(unsorted, unsorted[:, 0], 1, 3),
+              "sorted_z": synth.approx_sort(unsorted, unsorted[:, 2], 1, 3)}
+    xyz_u = torch.from_numpy(unsorted).cuda()
+    _, binned = binding.bin_points(xyz_u, 0, len(unsorted) // 128)
+    orders["gpu_binned_x_64_bins"] = binned.cpu().numpy()
+    out = torch.empty(2048, dtype=torch.int32, device="cuda")
+    rows = {}
+    for name, pts in orders.items():
+        xyz = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+        binding.fps(xyz, 2048, 0, out=out, stream=stream)
+        torch.cuda.synchronize()
+        ref = coverage_radius(pts, out.cpu().numpy())
+        row = {}
+        for m in (2, 8, 32):
+            binding.afps(xyz, 2048, m, 0, out=out, stream=stream)
+            torch.cuda.synchronize()
+            row["m%d" % m] = round(coverage_radius(pts, out.cpu().numpy()) / ref, 4)
+        rows[name] = row
+    times = {}
+    for n in (8192, 131072, 1048576):
+        pts = synth.lidar_scan(max(1, n // 64), 4, n=n)
+        xyz = torch.from_numpy(pts[rng.permutation(len(pts))]).cuda()
+        bins = min(8192, n // 128)
+        times["n%d_bins%d" % (n, bins)] = round(_median_ms(
+            torch, lambda: binding.bin_points(xyz, 0, bins, stream=stream), stream, reps), 4)
+    log("sortedness (AFPS coverage / FPS): %s; binning ms %s" % (rows, times))
+    return {"coverage_vs_fps": rows, "binning_ms": times,
+            "what": "object cloud N=8192, C=2048, start 0; AFPS coverage radius / plain FPS coverage radius "
+                    "on the same order; binning: shuffled LiDAR frames, points in binned order written"}
+
+
 def serving(torch, rates=(50, 200, 800), frames_npdu=160, frames_fps=24, pool=48, seed=1):
     """Open-loop Poisson streams of LiDAR frames (N uniform in [16384, 131072],
     C = N/8, M in {8, 16, 32}, k = 64) through the continuous-batching server,
@@ -412,6 +456,7 @@ def main():
         res["cycles_per_iteration"] = {k: round(v * 1e-3 * CLOCK_GHZ * 1e9 / iters[k], 1) for k, v in single.items()}
         res["cycles_per_iteration"]["note"] = "call time x 2.4 GHz / iterations of the longest sector (launch included)"
         res["object_n8192_c2048_sweep"], res["npdu_readings"] = object_sweep(torch, binding, synth, stream)
+        res["sortedness"] = sortedness(torch, binding, synth, stream)
 
     if not args.no_serve:
         res["serving"] = serving(torch)

@@ -550,7 +550,9 @@ int afps_set_plan_occupancy(float waves_per_simd) {
 size_t afps_bin_workspace_bytes(int32_t n, int32_t bins) {
     if (n < 1 || bins < 1 || bins > kMaxBins) return 0;
     const size_t chunks = ((size_t)n + kBinChunk - 1) / kBinChunk;
-    return sizeof(BinHeader) + (chunks * (size_t)bins * sizeof(uint32_t) + 255) / 256 * 256;
+    auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    // header, bin sizes / first positions, per-chunk histograms
+    return sizeof(BinHeader) + r256((size_t)bins * sizeof(uint32_t)) + r256(chunks * (size_t)bins * sizeof(uint32_t));
 }
 
 int afps_bin_points(const float* xyz, int32_t n, int32_t axis, int32_t bins, int32_t* perm, float* xyz_out,
@@ -569,7 +571,8 @@ int afps_bin_points(const float* xyz, int32_t n, int32_t axis, int32_t bins, int
     hipStream_t stream = (hipStream_t)stream_;
     const BinKernels k = bin_kernels();
     BinHeader* h = (BinHeader*)workspace;
-    uint32_t* hist = (uint32_t*)((char*)workspace + sizeof(BinHeader));
+    uint32_t* totals = (uint32_t*)((char*)workspace + sizeof(BinHeader));
+    uint32_t* hist = totals + ((size_t)bins * sizeof(uint32_t) + 255) / 256 * 64;
     int chunks = (int)(((int64_t)n + kBinChunk - 1) / kBinChunk);
     void* a0[] = {&h};
     AFPS_HIP(hipLaunchKernel(k.reset, dim3(1), dim3(64), a0, 0, stream));
@@ -577,10 +580,12 @@ int afps_bin_points(const float* xyz, int32_t n, int32_t axis, int32_t bins, int
     AFPS_HIP(hipLaunchKernel(k.range, dim3(std::min(chunks, 1024)), dim3(256), a1, 0, stream));
     void* a2[] = {(void*)&xyz, &n, &axis, &bins, &h, &hist};
     AFPS_HIP(hipLaunchKernel(k.count, dim3(chunks), dim3(256), a2, 0, stream));
-    void* a3[] = {&hist, &chunks, &bins};
-    AFPS_HIP(hipLaunchKernel(k.scan, dim3(1), dim3(1024), a3, 0, stream));
-    void* a4[] = {(void*)&xyz, &n, &axis, &bins, &h, &hist, &perm, &xyz_out};
-    AFPS_HIP(hipLaunchKernel(k.scatter, dim3(chunks), dim3(64), a4, 0, stream));
+    void* a3[] = {&hist, &totals, &chunks, &bins};
+    AFPS_HIP(hipLaunchKernel(k.scan_rows, dim3((bins + 3) / 4), dim3(256), a3, 0, stream));
+    void* a4[] = {&totals, &bins};
+    AFPS_HIP(hipLaunchKernel(k.scan_totals, dim3(1), dim3(1024), a4, 0, stream));
+    void* a5[] = {(void*)&xyz, &n, &axis, &bins, &h, &hist, &totals, &perm, &xyz_out};
+    AFPS_HIP(hipLaunchKernel(k.scatter, dim3(chunks), dim3(64), a5, 0, stream));
     return AFPS_OK;
 }
 

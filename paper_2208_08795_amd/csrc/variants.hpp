@@ -114,7 +114,7 @@ static_assert(sizeof(CheckResult) == 32, "check result layout");
 const void* check_points_kernel();
 
 // Binning along one axis (binning.hip): a stable counting sort by bin.
-constexpr int kBinChunk = 4096;   // points per histogram chunk (one scatter wave each)
+constexpr int kBinChunk = 1024;   // points per histogram chunk (one scatter wave each)
 constexpr int kMaxBins = 8192;    // bins counted in LDS
 struct BinHeader {
     uint32_t lo_key, hi_key;      // order keys of the smallest and largest coordinate
@@ -122,7 +122,7 @@ struct BinHeader {
 };
 static_assert(sizeof(BinHeader) == 256, "binning header");
 struct BinKernels {
-    const void *reset, *range, *count, *scan, *scatter;
+    const void *reset, *range, *count, *scan_rows, *scan_totals, *scatter;
 };
 BinKernels bin_kernels();
 

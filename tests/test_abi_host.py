@@ -60,7 +60,7 @@ def test_host_validation_without_gpu(L):
     # binning: sizes and arguments checked on the host
     assert L.afps_bin_workspace_bytes(0, 16) == 0 and L.afps_bin_workspace_bytes(10, 0) == 0
     assert L.afps_bin_workspace_bytes(10, 8193) == 0
-    assert L.afps_bin_workspace_bytes(8192, 1024) == 256 + 2 * 1024 * 4
+    assert L.afps_bin_workspace_bytes(8192, 1024) == 256 + 1024 * 4 + 8 * 1024 * 4   # 8 chunks of 1024 points
     assert L.afps_bin_points(None, 10, 0, 4, dummy, None, dummy, 1 << 20, None) == -1
     assert L.afps_bin_points(dummy, 10, 3, 4, dummy, None, dummy, 1 << 20, None) == -2
     assert L.afps_bin_points(dummy, 10, 0, 9000, dummy, None, dummy, 1 << 20, None) == -2
