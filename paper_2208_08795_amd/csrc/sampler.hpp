@@ -505,6 +505,192 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     }
 }
 
+// NPDU for narrow windows (k <= 64) on sectors of up to 4096 R points: the
+// loop of sample_sector_npdu_narrow with R registers of block maxima (block
+// 64 r + l in lane l of register r; a block's register is chosen by a scalar
+// binary search, so every register index is a constant) and, for sectors too
+// large for 16 bytes per point of LDS (XYZ_IN_LDS = false), only D in LDS and
+// the coordinates read from global memory (L2).
+template <int R, bool XYZ_IN_LDS, bool SHIFT>
+__device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restrict__ xyz, int n, int c,
+                                                          int k, int cur, int base,
+                                                          int32_t* __restrict__ out, uint32_t* lds,
+                                                          bool first_full) {
+    constexpr int kWords = XYZ_IN_LDS ? 4 : 1;   // LDS words per point: {D, x, y, z} or D
+    const int lane = threadIdx.x & 63;
+    const int nb = (n + 63) >> 6;
+    const int np = npdu_padded_points(n);
+    uint32_t* rec = static_cast<uint32_t*>(__builtin_assume_aligned(lds, 16));
+    const uint32_t init = __float_as_uint(kInitialDistance);
+    float fx = 0.f, fy = 0.f, fz = 0.f;   // start point, for the full first update
+    if (first_full) {
+        fx = xyz[3 * cur];
+        fy = xyz[3 * cur + 1];
+        fz = xyz[3 * cur + 2];
+    }
+
+    // Load: rounds of kLoadRound points per lane with every load in flight
+    // (coordinates are needed in LDS, or for the full first update).
+    if (XYZ_IN_LDS || first_full) {
+        for (int j0 = 0; j0 < np; j0 += kLoadRound * 64) {
+            float v[3 * kLoadRound];
+#pragma unroll
+            for (int u = 0; u < kLoadRound; ++u) {
+                const int jj = min(j0 + 64 * u + lane, n - 1);
+                v[3 * u] = xyz[3 * jj];
+                v[3 * u + 1] = xyz[3 * jj + 1];
+                v[3 * u + 2] = xyz[3 * jj + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadRound; ++u) {
+                const int jj = j0 + 64 * u + lane;
+                uint32_t d = jj < n ? init : 0u;
+                if (first_full && jj < n) d = min(init, sq_dist_bits(v[3 * u], v[3 * u + 1], v[3 * u + 2], fx, fy, fz));
+                if (jj < np) {
+                    if constexpr (XYZ_IN_LDS) {
+                        const uint4 r4 = make_uint4(d, __float_as_uint(v[3 * u]), __float_as_uint(v[3 * u + 1]),
+                                                    __float_as_uint(v[3 * u + 2]));
+                        __builtin_memcpy(rec + 4 * jj, &r4, 16);
+                    } else {
+                        rec[jj] = d;
+                    }
+                }
+            }
+        }
+    } else {
+        for (int j = lane; j < np; j += 64) rec[j] = j < n ? init : 0u;
+    }
+    sector_lds_ready();
+
+    uint32_t bm[R], bi[R];   // block maxima and their positions inside the block
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        bm[r] = 64 * r + lane < nb ? init : 0u;
+        bi[r] = 0u;
+    }
+    auto set_block = [&](int blk, uint32_t g, uint32_t i) {
+        with_slot<0, R - 1>(blk >> 6, [&](auto r) {
+            bm[r] = writelane(bm[r], g, blk & 63);
+            bi[r] = writelane(bi[r], i, blk & 63);
+        });
+    };
+    // The lowest index holding distance g: the lowest block, then its position.
+    auto lowest_with = [&](uint32_t g) {
+        int idx = 0;
+        bool found = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t hit = ballot(bm[r] == g);
+            if (!found && hit) {
+                const int l = (int)__builtin_ctzll(hit);
+                idx = 64 * (64 * r + l) + (int)readlane(bi[r], l);
+                found = true;
+            }
+        }
+        return idx;
+    };
+    const int below = k >> 1, above = k - (k >> 1);
+    uint32_t picks = (uint32_t)cur;   // sector-local pick of step s in lane s
+    int s_first = 1;
+    if (first_full) {
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t d = rec[kWords * (64 * b + lane)];
+            const uint32_t g = wave_max(d);
+            set_block(b, g, (uint32_t)__builtin_ctzll(ballot(d == g)));
+        }
+        if (c > 1) {
+            uint32_t mx = 0u;
+#pragma unroll
+            for (int r = 0; r < R; ++r) mx = max(mx, bm[r]);
+            cur = lowest_with(wave_max(mx));
+            picks = writelane(picks, (uint32_t)cur, 1);
+            s_first = 2;
+        }
+    }
+
+    auto step = [&](int s) {
+        float px, py, pz;
+        if constexpr (XYZ_IN_LDS) {
+            px = __uint_as_float(rec[4 * cur + 1]);
+            py = __uint_as_float(rec[4 * cur + 2]);
+            pz = __uint_as_float(rec[4 * cur + 3]);
+        } else {
+            px = xyz[3 * cur];
+            py = xyz[3 * cur + 1];
+            pz = xyz[3 * cur + 2];
+        }
+        int lo, hi;
+        if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
+            lo = cur - below;
+            hi = cur + above;
+            if (lo < 0) {
+                hi -= lo;
+                lo = 0;
+            }
+            if (hi > n - 1) {
+                lo = max(0, lo - (hi - (n - 1)));
+                hi = n - 1;
+            }
+        } else {
+            lo = max(0, cur - below);
+            hi = min(n - 1, cur + above);
+        }
+        const int blo = lo >> 6;
+        const int j0 = 64 * blo + lane, j1 = j0 + 64;
+        uint32_t a_d, b_d;
+        float ax, ay, az, bx, by, bz;
+        if constexpr (XYZ_IN_LDS) {
+            uint4 A, B;
+            __builtin_memcpy(&A, rec + 4 * j0, 16);
+            __builtin_memcpy(&B, rec + 4 * j1, 16);
+            a_d = A.x; ax = __uint_as_float(A.y); ay = __uint_as_float(A.z); az = __uint_as_float(A.w);
+            b_d = B.x; bx = __uint_as_float(B.y); by = __uint_as_float(B.z); bz = __uint_as_float(B.w);
+        } else {
+            a_d = rec[j0];
+            b_d = rec[j1];
+            const int ja = min(j0, n - 1), jb = min(j1, n - 1);   // padding points read a real one
+            ax = xyz[3 * ja]; ay = xyz[3 * ja + 1]; az = xyz[3 * ja + 2];
+            bx = xyz[3 * jb]; by = xyz[3 * jb + 1]; bz = xyz[3 * jb + 2];
+        }
+
+        uint32_t mo = 0u;   // best of the blocks outside the window's two
+#pragma unroll
+        for (int r = 0; r < R; ++r) mo = max(mo, (uint32_t)(64 * r + lane - blo) > 1u ? bm[r] : 0u);
+        const uint32_t g_out = wave_max(mo);
+
+        const int t = lane - (lo & 63);
+        const int span = hi - lo;
+        const uint32_t e0 = min(a_d, sq_dist_bits(ax, ay, az, px, py, pz));
+        const uint32_t e1 = min(b_d, sq_dist_bits(bx, by, bz, px, py, pz));
+        const uint32_t d0 = (uint32_t)t <= (uint32_t)span ? e0 : a_d;
+        const uint32_t d1 = t <= span - 64 ? e1 : b_d;
+        rec[kWords * j0] = d0;
+        rec[kWords * j1] = d1;
+
+        uint32_t g0, g1;
+        wave_max2(d0, d1, g0, g1);
+        const uint32_t i0 = (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+        const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+        // Block blo+1 may be the padding block (maximum 0, never the lowest
+        // holder of a maximum); past the registers it is not recorded.
+        if (blo + 1 < 64 * R) set_block(blo + 1, g1, i1);
+        set_block(blo, g0, i0);
+        cur = lowest_with(max(g_out, max(g0, g1)));
+        picks = writelane(picks, (uint32_t)cur, s);
+    };
+
+    for (int i0 = 0; i0 < c; i0 += 64) {
+        const int s_end = min(64, c - i0);
+        int s = i0 == 0 ? s_first : 0;
+        for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
+            step(s);
+            step(s + 1);
+        }
+        if (s < s_end) step(s);
+        if (lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
+    }
+}
+
 // NPDU on one sector (Sec. III-C), one wave.
 //   xyz   : the sector's first point in global memory
 //   n, c  : points and samples (1 <= c <= n <= 4096*R)
@@ -531,12 +717,15 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
                                                    int flags) {
     const bool first_full = (flags & kNpduFirstFull) != 0;
     const bool shift = (flags & kNpduShiftEdges) != 0;
-    if constexpr (R == 1 && XYZ_IN_LDS) {
-        if (k <= 64) {
+    if (k <= 64) {   // the window lies in two adjacent blocks
+        if constexpr (R == 1 && XYZ_IN_LDS) {
             if (shift) sample_sector_npdu_narrow<true>(xyz, n, c, k, cur, base, out, lds, first_full);
             else sample_sector_npdu_narrow<false>(xyz, n, c, k, cur, base, out, lds, first_full);
-            return;
+        } else {
+            if (shift) sample_sector_npdu_blocks<R, XYZ_IN_LDS, true>(xyz, n, c, k, cur, base, out, lds, first_full);
+            else sample_sector_npdu_blocks<R, XYZ_IN_LDS, false>(xyz, n, c, k, cur, base, out, lds, first_full);
         }
+        return;
     }
     const int lane = threadIdx.x & 63;
     const int nb = (n + 63) >> 6;                 // blocks holding points
