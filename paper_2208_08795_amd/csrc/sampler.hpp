@@ -116,6 +116,13 @@ __device__ __forceinline__ void take_better(uint32_t g, uint32_t i, uint32_t& gb
     gb = t ? g : gb;
     ib = t ? i : ib;
 }
+// v_writelane_b32 (clang declares no builtin for it): `old` with lane `lane`
+// (wave-uniform) replaced by the wave-uniform `value`.
+extern "C" __device__ int afps_llvm_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane");
+__device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t value, int lane) {
+    return (uint32_t)afps_llvm_writelane((int)value, lane, (int)old);
+}
+
 // Whole-wave min, returned wave-uniform (rows outside the mask see UINT_MAX).
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
     v = row_min(v);
@@ -303,29 +310,28 @@ __device__ __forceinline__ void sample_sector(const float* __restrict__ xyz, int
     load_points<P, T, DL>(xyz, n, ns, t, X, Y, Z, D);
 
     float px = xyz[3 * cur + 0], py = xyz[3 * cur + 1], pz = xyz[3 * cur + 2];
-    // Picks are buffered one per lane of wave 0 (pick i in lane i mod 64) and
-    // written 64 at a time.
-    uint32_t picks = (uint32_t)(base + cur);
-
-    for (int i = 1; i < c; ++i) {
+    // Picks go out 64 at a time (wave 0 writes); two steps per loop trip with
+    // a scalar counter, as in the NPDU loop.
+    uint32_t picks = (uint32_t)cur;   // sector-local pick of step s in lane s (every wave)
+    auto step = [&](int s) {
         const Pick mine = update_and_pick<P, T, DL>(ns, w, lane, X, Y, Z, D, px, py, pz);
-        const Pick p = combine_waves<W>(mine, lds, i & 1, w, lane);
+        const Pick p = combine_waves<W>(mine, lds, s & 1, w, lane);
         cur = (int)p.idx;
         px = p.x; py = p.y; pz = p.z;
-        const int slot = i & 63;
-        picks = lane == slot ? (uint32_t)(base + cur) : picks;
-        if (slot == 63 && w == 0) out[i - 63 + lane] = (int32_t)picks;
+        picks = writelane(picks, (uint32_t)cur, s);
+    };
+    for (int i0 = 0; i0 < c; i0 += 64) {
+        const int s_end = min(64, c - i0);
+        int s = i0 == 0 ? 1 : 0;
+        for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
+            step(s);
+            step(s + 1);
+        }
+        if (s < s_end) step(s);
+        if (w == 0 && lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
     }
-    const int tail = (c - 1) & 63;   // picks of the last, partial group
-    if (w == 0 && tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
 }
 
-// v_writelane_b32 (clang declares no builtin for it): `old` with lane `lane`
-// (wave-uniform) replaced by the wave-uniform `value`.
-extern "C" __device__ int afps_llvm_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane");
-__device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t value, int lane) {
-    return (uint32_t)afps_llvm_writelane((int)value, lane, (int)old);
-}
 
 // A sector of the NPDU samplers belongs to one wave: its LDS stores need only
 // have completed before its own later loads, with no workgroup barrier (other
@@ -505,12 +511,13 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     }
 }
 
-// NPDU for narrow windows (k <= 64) on sectors of up to 4096 R points: the
-// loop of sample_sector_npdu_narrow with R registers of block maxima (block
-// 64 r + l in lane l of register r; a block's register is chosen by a scalar
-// binary search, so every register index is a constant) and, for sectors too
-// large for 16 bytes per point of LDS (XYZ_IN_LDS = false), only D in LDS and
-// the coordinates read from global memory (L2).
+// NPDU on sectors of up to 4096 R points, any window: the loop of
+// sample_sector_npdu_narrow with R registers of block maxima (block 64 r + l
+// in lane l of register r; a block's register is chosen by a scalar binary
+// search, so every register index is a constant), the window's blocks
+// re-reduced two at a time, and, for sectors too large for 16 bytes per point
+// of LDS (XYZ_IN_LDS = false), only D in LDS and the coordinates read from
+// global memory (L2).
 template <int R, bool XYZ_IN_LDS, bool SHIFT>
 __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restrict__ xyz, int n, int c,
                                                           int k, int cur, int base,
@@ -608,7 +615,45 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
         }
     }
 
-    auto step = [&](int s) {
+    // Update and re-reduce the two blocks b0, b0 + 1 (window points [lo, hi]
+    // only); returns the larger block maximum.
+    auto update_pair = [&](int b0, int lo, int span, float px, float py, float pz) {
+        const int j0 = 64 * b0 + lane, j1 = j0 + 64;
+        uint32_t a_d, b_d;
+        float ax, ay, az, bx, by, bz;
+        if constexpr (XYZ_IN_LDS) {
+            uint4 A, B;
+            __builtin_memcpy(&A, rec + 4 * j0, 16);
+            __builtin_memcpy(&B, rec + 4 * j1, 16);
+            a_d = A.x; ax = __uint_as_float(A.y); ay = __uint_as_float(A.z); az = __uint_as_float(A.w);
+            b_d = B.x; bx = __uint_as_float(B.y); by = __uint_as_float(B.z); bz = __uint_as_float(B.w);
+        } else {
+            a_d = rec[j0];
+            b_d = rec[j1];
+            const int ja = min(j0, n - 1), jb = min(j1, n - 1);   // padding points read a real one
+            ax = xyz[3 * ja]; ay = xyz[3 * ja + 1]; az = xyz[3 * ja + 2];
+            bx = xyz[3 * jb]; by = xyz[3 * jb + 1]; bz = xyz[3 * jb + 2];
+        }
+        const uint32_t e0 = min(a_d, sq_dist_bits(ax, ay, az, px, py, pz));
+        const uint32_t e1 = min(b_d, sq_dist_bits(bx, by, bz, px, py, pz));
+        const uint32_t d0 = (uint32_t)(j0 - lo) <= (uint32_t)span ? e0 : a_d;
+        const uint32_t d1 = (uint32_t)(j1 - lo) <= (uint32_t)span ? e1 : b_d;
+        rec[kWords * j0] = d0;
+        rec[kWords * j1] = d1;
+        uint32_t g0, g1;
+        wave_max2(d0, d1, g0, g1);
+        const uint32_t i0 = (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+        const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+        // Block b0+1 may be the padding block (maximum 0, never the lowest
+        // holder of a maximum); past the registers it is not recorded.
+        if (b0 + 1 < 64 * R) set_block(b0 + 1, g1, i1);
+        set_block(b0, g0, i0);
+        return max(g0, g1);
+    };
+
+    // One iteration; NARROW (k <= 64: the window lies in two adjacent blocks)
+    // fixes the number of block pairs at one.
+    auto step = [&](int s, auto narrow) {
         float px, py, pz;
         if constexpr (XYZ_IN_LDS) {
             px = __uint_as_float(rec[4 * cur + 1]);
@@ -636,80 +681,53 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
             hi = min(n - 1, cur + above);
         }
         const int blo = lo >> 6;
-        const int j0 = 64 * blo + lane, j1 = j0 + 64;
-        uint32_t a_d, b_d;
-        float ax, ay, az, bx, by, bz;
-        if constexpr (XYZ_IN_LDS) {
-            uint4 A, B;
-            __builtin_memcpy(&A, rec + 4 * j0, 16);
-            __builtin_memcpy(&B, rec + 4 * j1, 16);
-            a_d = A.x; ax = __uint_as_float(A.y); ay = __uint_as_float(A.z); az = __uint_as_float(A.w);
-            b_d = B.x; bx = __uint_as_float(B.y); by = __uint_as_float(B.z); bz = __uint_as_float(B.w);
-        } else {
-            a_d = rec[j0];
-            b_d = rec[j1];
-            const int ja = min(j0, n - 1), jb = min(j1, n - 1);   // padding points read a real one
-            ax = xyz[3 * ja]; ay = xyz[3 * ja + 1]; az = xyz[3 * ja + 2];
-            bx = xyz[3 * jb]; by = xyz[3 * jb + 1]; bz = xyz[3 * jb + 2];
-        }
+        // the window's blocks [blo, hi >> 6], re-reduced in pairs
+        const int pairs = decltype(narrow)::value ? 1 : ((hi >> 6) - blo + 2) >> 1;
 
-        uint32_t mo = 0u;   // best of the blocks outside the window's two
+        uint32_t mo = 0u;   // best of the blocks outside the re-reduced pairs
 #pragma unroll
-        for (int r = 0; r < R; ++r) mo = max(mo, (uint32_t)(64 * r + lane - blo) > 1u ? bm[r] : 0u);
-        const uint32_t g_out = wave_max(mo);
-
-        const int t = lane - (lo & 63);
-        const int span = hi - lo;
-        const uint32_t e0 = min(a_d, sq_dist_bits(ax, ay, az, px, py, pz));
-        const uint32_t e1 = min(b_d, sq_dist_bits(bx, by, bz, px, py, pz));
-        const uint32_t d0 = (uint32_t)t <= (uint32_t)span ? e0 : a_d;
-        const uint32_t d1 = t <= span - 64 ? e1 : b_d;
-        rec[kWords * j0] = d0;
-        rec[kWords * j1] = d1;
-
-        uint32_t g0, g1;
-        wave_max2(d0, d1, g0, g1);
-        const uint32_t i0 = (uint32_t)__builtin_ctzll(ballot(d0 == g0));
-        const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
-        // Block blo+1 may be the padding block (maximum 0, never the lowest
-        // holder of a maximum); past the registers it is not recorded.
-        if (blo + 1 < 64 * R) set_block(blo + 1, g1, i1);
-        set_block(blo, g0, i0);
-        cur = lowest_with(max(g_out, max(g0, g1)));
+        for (int r = 0; r < R; ++r) mo = max(mo, (uint32_t)(64 * r + lane - blo) >= (uint32_t)(2 * pairs) ? bm[r] : 0u);
+        uint32_t best = wave_max(mo);
+        best = max(best, update_pair(blo, lo, hi - lo, px, py, pz));
+        if constexpr (!decltype(narrow)::value)
+            for (int p = 1; p < pairs; ++p) best = max(best, update_pair(blo + 2 * p, lo, hi - lo, px, py, pz));
+        cur = lowest_with(best);
         picks = writelane(picks, (uint32_t)cur, s);
     };
 
-    for (int i0 = 0; i0 < c; i0 += 64) {
-        const int s_end = min(64, c - i0);
-        int s = i0 == 0 ? s_first : 0;
-        for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
-            step(s);
-            step(s + 1);
+    auto run = [&](auto narrow) {
+        for (int i0 = 0; i0 < c; i0 += 64) {
+            const int s_end = min(64, c - i0);
+            int s = i0 == 0 ? s_first : 0;
+            for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
+                step(s, narrow);
+                step(s + 1, narrow);
+            }
+            if (s < s_end) step(s, narrow);
+            if (lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
         }
-        if (s < s_end) step(s);
-        if (lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
-    }
+    };
+    if (k <= 64) run(std::integral_constant<bool, true>{});
+    else run(std::integral_constant<bool, false>{});
 }
 
 // NPDU on one sector (Sec. III-C), one wave.
 //   xyz   : the sector's first point in global memory
 //   n, c  : points and samples (1 <= c <= n <= 4096*R)
 //   k     : window parameter, 0 <= k <= 2n; the window of sample `cur` is
-//           [cur - floor(k/2), cur + ceil(k/2)] cut to [0, n-1]
+//           [cur - floor(k/2), cur + ceil(k/2)] cut to [0, n-1] (or moved
+//           inside it, kNpduShiftEdges)
 //   cur   : local start point
 //   lds   : npdu_lds_words(n, XYZ_IN_LDS) words of shared memory
-// The sector is cut into blocks of 64 consecutive points; lane l of block
-// register r describes block 64r + l: its maximum distance (bm) and the lowest
-// index reaching it (bi).  Distances only decrease and only inside the
-// window, so every block outside the window keeps its (bm, bi).  Per
-// iteration: one LDS round trip brings the new sample's coordinates and the
-// two blocks holding the window (x, y, z, D); while it is in flight the wave
-// reduces the out-of-window blocks; then it updates the window points,
-// re-reduces the two blocks from registers and takes the maximum, ties to the
-// lowest index.  LDS holds x, y, z and D as separate arrays padded with one
-// empty block (D = 0, never a window point), so block reads need no bounds
-// test.  XYZ_IN_LDS = false reads coordinates from global memory (L2) and
-// keeps only D in LDS, for sectors too large for 16 bytes per point.
+//   flags : kNpduFirstFull, kNpduShiftEdges
+// The sector is cut into blocks of 64 consecutive points whose maxima (and
+// the lowest index reaching them) live one block per lane.  Distances only
+// decrease and only inside the window, so every other block keeps its
+// maximum; per iteration the wave re-reduces the window's blocks and takes the
+// lowest block holding the overall maximum.  LDS is padded with one empty
+// block (D = 0, never a window point), so block reads need no bounds test.
+// XYZ_IN_LDS = false reads coordinates from global memory (L2) and keeps only
+// D in LDS, for sectors too large for 16 bytes per point.
 template <int R, bool XYZ_IN_LDS>
 __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz, int n, int c,
                                                    int k, int cur, int base,
@@ -717,213 +735,15 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
                                                    int flags) {
     const bool first_full = (flags & kNpduFirstFull) != 0;
     const bool shift = (flags & kNpduShiftEdges) != 0;
-    if (k <= 64) {   // the window lies in two adjacent blocks
-        if constexpr (R == 1 && XYZ_IN_LDS) {
+    if constexpr (R == 1 && XYZ_IN_LDS) {
+        if (k <= 64) {   // the window lies in two adjacent blocks
             if (shift) sample_sector_npdu_narrow<true>(xyz, n, c, k, cur, base, out, lds, first_full);
             else sample_sector_npdu_narrow<false>(xyz, n, c, k, cur, base, out, lds, first_full);
-        } else {
-            if (shift) sample_sector_npdu_blocks<R, XYZ_IN_LDS, true>(xyz, n, c, k, cur, base, out, lds, first_full);
-            else sample_sector_npdu_blocks<R, XYZ_IN_LDS, false>(xyz, n, c, k, cur, base, out, lds, first_full);
-        }
-        return;
-    }
-    const int lane = threadIdx.x & 63;
-    const int nb = (n + 63) >> 6;                 // blocks holding points
-    const int np = npdu_padded_points(n);
-    float* sx = reinterpret_cast<float*>(lds);
-    float* sy = sx + np;
-    float* sz = sy + np;
-    uint32_t* sd = lds + (XYZ_IN_LDS ? 3 * np : 0);
-
-    if constexpr (XYZ_IN_LDS) {
-        for (int j0 = 0; j0 < np; j0 += kLoadRound * 64) {   // as in the narrow sampler
-            float v[3 * kLoadRound];
-#pragma unroll
-            for (int u = 0; u < kLoadRound; ++u) {
-                const int jj = min(j0 + 64 * u + lane, n - 1);
-                v[3 * u] = xyz[3 * jj];
-                v[3 * u + 1] = xyz[3 * jj + 1];
-                v[3 * u + 2] = xyz[3 * jj + 2];
-            }
-#pragma unroll
-            for (int u = 0; u < kLoadRound; ++u) {
-                const int jj = j0 + 64 * u + lane;
-                if (jj < np) {
-                    sx[jj] = v[3 * u]; sy[jj] = v[3 * u + 1]; sz[jj] = v[3 * u + 2];
-                }
-            }
+            return;
         }
     }
-    // D starts at 1e10, or (kNpduFirstFull) at the distance from the start
-    // point: the full update of the first iteration.
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    if (first_full) {
-        if constexpr (XYZ_IN_LDS) { fx = sx[cur]; fy = sy[cur]; fz = sz[cur]; }
-        else { fx = xyz[3 * cur]; fy = xyz[3 * cur + 1]; fz = xyz[3 * cur + 2]; }
-    }
-    for (int j = lane; j < np; j += 64) {
-        uint32_t d = j < n ? __float_as_uint(kInitialDistance) : 0u;
-        if (first_full && j < n) {
-            float x, y, z;
-            if constexpr (XYZ_IN_LDS) { x = sx[j]; y = sy[j]; z = sz[j]; }
-            else { x = xyz[3 * j]; y = xyz[3 * j + 1]; z = xyz[3 * j + 2]; }
-            d = min(d, sq_dist_bits(x, y, z, fx, fy, fz));
-        }
-        sd[j] = d;
-    }
-    sector_lds_ready();
-
-    uint32_t bm[R], bi[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int blk = 64 * r + lane;
-        bm[r] = blk < nb ? __float_as_uint(kInitialDistance) : 0u;
-        bi[r] = blk < nb ? (uint32_t)(64 * blk) : 0xFFFFFFFFu;
-    }
-    const int below = k >> 1, above = k - (k >> 1);
-    // Picks are buffered one per lane (pick i in lane i mod 64) and written
-    // 64 at a time.
-    uint32_t picks = (uint32_t)(base + cur);
-    int i_first = 1;
-    if (first_full) {
-        // Every block's maximum and its lowest index after the full update,
-        // then the pick of iteration 1.
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            for (int l = 0; l < 64 && 64 * r + l < nb; ++l) {
-                const int blk = 64 * r + l;
-                const uint32_t d = sd[64 * blk + lane];
-                const uint32_t g = wave_max(d);
-                bm[r] = writelane(bm[r], g, l);
-                bi[r] = writelane(bi[r], (uint32_t)(64 * blk) + (uint32_t)__builtin_ctzll(ballot(d == g)), l);
-            }
-        }
-        if (c > 1) {
-            uint32_t mx = 0u;
-#pragma unroll
-            for (int r = 0; r < R; ++r) mx = max(mx, bm[r]);
-            const uint32_t g = wave_max(mx);
-            int pick = -1;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint64_t hit = ballot(bm[r] == g);
-                if (pick < 0 && hit) pick = (int)readlane(bi[r], (int)__builtin_ctzll(hit));
-            }
-            cur = pick;
-            picks = lane == 1 ? (uint32_t)(base + cur) : picks;
-            i_first = 2;
-        }
-    }
-
-    for (int i = i_first; i < c; ++i) {
-        int lo = cur - below, hi = cur + above;
-        if (shift) {   // kNpduShiftEdges: keep the window's size inside the sector
-            if (lo < 0) {
-                hi -= lo;
-                lo = 0;
-            }
-            if (hi > n - 1) {
-                lo -= hi - (n - 1);
-                hi = n - 1;
-            }
-        }
-        lo = max(0, lo);
-        hi = min(n - 1, hi);
-        const int blo = lo >> 6, bhi = hi >> 6;
-        const uint32_t span = (uint32_t)(hi - lo);
-
-        // One round of loads: the sample's coordinates and the first two
-        // window blocks (x, y, z, D).
-        const int j0 = 64 * blo + lane, j1 = j0 + 64;
-        uint32_t d0 = sd[j0], d1 = sd[j1];
-        float px, py, pz, x0, y0, z0, x1, y1, z1;
-        if constexpr (XYZ_IN_LDS) {
-            px = sx[cur]; py = sy[cur]; pz = sz[cur];
-            x0 = sx[j0]; y0 = sy[j0]; z0 = sz[j0];
-            x1 = sx[j1]; y1 = sy[j1]; z1 = sz[j1];
-        } else {
-            px = xyz[3 * cur]; py = xyz[3 * cur + 1]; pz = xyz[3 * cur + 2];
-            const bool ok0 = j0 < n, ok1 = j1 < n;
-            x0 = ok0 ? xyz[3 * j0] : 0.f; y0 = ok0 ? xyz[3 * j0 + 1] : 0.f; z0 = ok0 ? xyz[3 * j0 + 2] : 0.f;
-            x1 = ok1 ? xyz[3 * j1] : 0.f; y1 = ok1 ? xyz[3 * j1 + 1] : 0.f; z1 = ok1 ? xyz[3 * j1 + 2] : 0.f;
-        }
-
-        // Best block outside the window's blocks [blo, bhi] (maximum, then the
-        // lowest index); independent of the loads above, so it runs while
-        // they are in flight.
-        uint32_t g_best, i_best = 0xFFFFFFFFu;
-        {
-            const uint32_t nblk = (uint32_t)(bhi - blo);
-            uint32_t mo = 0u;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                mo = max(mo, (uint32_t)(64 * r + lane - blo) > nblk ? bm[r] : 0u);
-            g_best = wave_max(mo);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint64_t hit = ballot((uint32_t)(64 * r + lane - blo) > nblk && bm[r] == g_best);
-                if (i_best == 0xFFFFFFFFu && hit) i_best = readlane(bi[r], (int)__builtin_ctzll(hit));
-            }
-        }
-
-        // Window update of the two blocks (points outside the window keep D).
-        {
-            const uint32_t e0 = min(d0, sq_dist_bits(x0, y0, z0, px, py, pz));
-            const uint32_t e1 = min(d1, sq_dist_bits(x1, y1, z1, px, py, pz));
-            d0 = (uint32_t)(j0 - lo) <= span ? e0 : d0;
-            d1 = (uint32_t)(j1 - lo) <= span ? e1 : d1;
-            sd[j0] = d0;
-            sd[j1] = d1;
-        }
-        // Re-reduce both blocks and record them in their lanes.  The second
-        // may be the empty padding block (block nb): it is not recorded, and
-        // its candidates lie past n, so they never beat a real point.
-        {
-            uint32_t g0, g1;
-            wave_max2(d0, d1, g0, g1);
-            const uint32_t i0 = (uint32_t)(64 * blo) + (uint32_t)__builtin_ctzll(ballot(d0 == g0));
-            const uint32_t i1 = (uint32_t)(64 * blo + 64) + (uint32_t)__builtin_ctzll(ballot(d1 == g1));
-            // Block blo precedes block blo+1, so between the two a tie keeps
-            // the first; only the merge with the out-of-window best needs
-            // the index comparison.
-            const bool later = g1 > g0;
-            take_better(later ? g1 : g0, later ? i1 : i0, g_best, i_best);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int blk = 64 * r + lane;
-                const bool second = blk == blo + 1 && blk < nb;
-                bm[r] = blk == blo ? g0 : (second ? g1 : bm[r]);
-                bi[r] = blk == blo ? i0 : (second ? i1 : bi[r]);
-            }
-        }
-        // Windows wider than two blocks (k > 64): the remaining blocks.
-        for (int b = blo + 2; b <= bhi; ++b) {
-            const int j = 64 * b + lane;
-            uint32_t d = sd[j];
-            if ((uint32_t)(j - lo) <= span) {
-                float x, y, z;
-                if constexpr (XYZ_IN_LDS) { x = sx[j]; y = sy[j]; z = sz[j]; }
-                else { x = xyz[3 * j]; y = xyz[3 * j + 1]; z = xyz[3 * j + 2]; }
-                d = min(d, sq_dist_bits(x, y, z, px, py, pz));
-                sd[j] = d;
-            }
-            const uint32_t g = wave_max(d);
-            const uint32_t idx = (uint32_t)(64 * b) + (uint32_t)__builtin_ctzll(ballot(d == g));
-            take_better(g, idx, g_best, i_best);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int blk = 64 * r + lane;
-                bm[r] = blk == b ? g : bm[r];
-                bi[r] = blk == b ? idx : bi[r];
-            }
-        }
-        cur = (int)i_best;
-        const int slot = i & 63;
-        picks = lane == slot ? (uint32_t)(base + cur) : picks;
-        if (slot == 63) out[i - 63 + lane] = (int32_t)picks;
-    }
-    const int tail = (c - 1) & 63;   // picks of the last, partial group
-    if (tail != 63 && lane <= tail) out[(c - 1) - tail + lane] = (int32_t)picks;
+    if (shift) sample_sector_npdu_blocks<R, XYZ_IN_LDS, true>(xyz, n, c, k, cur, base, out, lds, first_full);
+    else sample_sector_npdu_blocks<R, XYZ_IN_LDS, false>(xyz, n, c, k, cur, base, out, lds, first_full);
 }
 
 }  // namespace afps

@@ -152,6 +152,24 @@ def test_npdu_narrow_window_edges(B, torch_dev):
             _check(B, torch, dev, pts, n, 1, k, n - 1, label="narrow-small")
 
 
+@pytest.mark.parametrize("q", [1, 2, 4, 8])
+def test_npdu_wide_windows(B, torch_dev, q):
+    """Windows wider than two blocks (re-reduced two blocks at a time): an
+    even and an odd number of window blocks, windows reaching the padding
+    block past the last point and the last register, windows covering the
+    whole sector, both edge readings, exact ties."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(900 + q)
+    for n in (4096 * q, 4096 * q - 37):
+        pts = synth.object_cloud(n, seed=n)
+        ties = rng.integers(0, 3, (n, 3)).astype(np.float32)
+        for p, k, flags, start in [(pts, 65, 0, n - 1), (pts, 128, 0, 0), (pts, 191, 2, n // 2),
+                                   (pts, 256, 0, n - 1), (pts, 700, 1, 3), (pts, 1000, 3, n - 5),
+                                   (ties, 200, 0, n // 3), (pts, 2 * n, 0, 7)]:
+            _check(B, torch, dev, p, min(n, 1200), 1, k, start, variant=(1, q), label="wide-q%d" % q,
+                   flags=flags)
+
+
 READING_FLAGS = (1, 2, 3, 4, 5, 6, 7)   # full first update, shifted windows, k counting the sample
 
 
