@@ -14,9 +14,10 @@
 //   LDS (double-buffered by iteration parity: one barrier per iteration).
 //
 // sample_sector_npdu (Sec. III-C: update only the window around the sample)
-//   One wave, sector in LDS (x, y, z and D), cut into blocks of 64 points
-//   whose maxima live one per lane; per iteration one LDS round trip, the
-//   window update, and a re-reduction of the one or two window blocks only.
+//   One wave, sector in LDS (x, y, z and D, or D only for large sectors), cut
+//   into blocks of 64 points whose maxima live one per lane; per iteration
+//   one LDS round trip, the window update, and a re-reduction of the window's
+//   blocks only (two at a time).
 //
 // Distances are kept as fp32 bit patterns: every distance is >= +0, so
 // unsigned order equals float order and min / max are exact integer ops.
