@@ -284,6 +284,21 @@ def test_batched_uneven_npdu_and_graph(B, torch_dev):
                 graph_replays=3)
 
 
+@pytest.mark.parametrize("occupancy", [0.0, 1.0, 2.0, 4.0])
+def test_batch_of_256_every_cloud(B, torch_dev, occupancy):
+    """The timed batch at its full size (256 object clouds, N log-uniform in
+    [1024, 32768], C = N/4, AFPS M = 8, NPDU k = 32, the same seed), every
+    cloud against the oracle, under each plan occupancy the tuner can pick."""
+    torch, dev = torch_dev
+    clouds = synth.batch_of_objects(256, seed=0)
+    cs = [len(p) // 4 for p in clouds]
+    B.set_plan_occupancy(occupancy)
+    try:
+        _batch_case(B, torch, dev, clouds, cs, [8] * 256, [32] * 256, [0] * 256, graph_replays=2)
+    finally:
+        B.set_plan_occupancy(0.0)
+
+
 def test_batched_mixed_variants(B, torch_dev):
     """Plain FPS, AFPS and NPDU clouds of uneven size in one plan (several
     persistent launches on helper streams)."""
