@@ -137,19 +137,20 @@ typedef struct afps_plan afps_plan;
  */
 int afps_plan_create(const afps_cloud_desc *descs, int32_t batch, afps_plan **plan);
 
-/* Device workspace bytes the plan needs (counters, queue table, work items). */
+/* Device workspace bytes the plan needs (counters, queue and seed tables, work items). */
 size_t afps_plan_workspace_bytes(const afps_plan *plan);
 
 /*
  * Workspace bytes of a plan with `items` work items in total (one per sector,
- * i.e. the sum of m over the batch): a 2.75 KB header of queue counters and
- * the NPDU queue table plus 40 bytes per item, rounded up to 256.  Lets a caller reserve device memory before building
+ * i.e. the sum of m over the batch): a 34.75 KB header of queue counters, the
+ * NPDU queue table and the table of each pooled wave's first sector, plus 40
+ * bytes per item, rounded up to 256.  Lets a caller reserve device memory before building
  * the plan.  Host-only arithmetic; 0 for items <= 0.
  */
 size_t afps_workspace_bytes_for_items(int32_t items);
 
 /*
- * Copy the plan's tables (NPDU queues, work items) into `workspace` (DEVICE,
+ * Copy the plan's tables (NPDU queues and first sectors, work items) into `workspace` (DEVICE,
  * >= the size above, 256-byte aligned) on `stream`.  Must precede
  * afps_plan_launch with that workspace; the tables stay valid until
  * overwritten.

@@ -625,12 +625,13 @@ struct Bucket {
 };
 
 // Workspace of a plan: [bucket counters | pool queue counters | pool queue
-// table | work items].
+// table | pool seeds | work items].
 constexpr size_t kCounterBytes = 256;                                   // one per bucket
 constexpr int kMaxBuckets = (int)(kCounterBytes / sizeof(unsigned));
 constexpr size_t kPoolCounterOffset = kCounterBytes;                    // one per pool queue
 constexpr size_t kPoolTableOffset = kPoolCounterOffset + kMaxPoolQueues * sizeof(unsigned);
-constexpr size_t kItemsOffset = kPoolTableOffset + kMaxPoolQueues * sizeof(PoolQueue);
+constexpr size_t kPoolSeedOffset = kPoolTableOffset + kMaxPoolQueues * sizeof(PoolQueue);
+constexpr size_t kItemsOffset = kPoolSeedOffset + (size_t)kMaxPoolSeedGroups * kMaxPoolWaves * sizeof(PoolSeed);
 static_assert(kItemsOffset % 256 == 0, "work items start 256-byte aligned");
 constexpr int kResetWords = (int)(kPoolTableOffset / sizeof(unsigned));
 
@@ -643,6 +644,7 @@ struct afps_plan {
     std::vector<WorkItem> items;
     std::vector<Bucket> buckets;
     std::vector<PoolQueue> queues;    // pool queues, highest priority first
+    std::vector<PoolSeed> seeds;      // first sector of each pool wave (workgroup-major)
     std::vector<CheckSeg> clouds;     // each descriptor's points, for the optional input check
     int pool_pages = 0;
     size_t ws_bytes = 0;
@@ -792,6 +794,31 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         bk.block = 64 * pe->waves;
         bk.lds_bytes = plan->pool_pages * kPoolPageBytes;
         bk.grid = std::min(ds->cu_count, bk.count);
+        // Seeds: the queue policy of the kernel played out on the host for
+        // the moment every wave starts (wave w of every workgroup, then wave
+        // w + 1, each taking the first queue with sectors left that fits its
+        // workgroup's pages), so that a launch starts without a rush of every
+        // wave on the same queue counter.  A workgroup's seeds sit in
+        // consecutive pages from page 0; the seeded sectors are the front of
+        // their queues, which then start after them.
+        const int sg = std::min(bk.grid, kMaxPoolSeedGroups);
+        plan->seeds.assign((size_t)sg * pe->waves, PoolSeed{-1, 0});
+        std::vector<int> taken(plan->queues.size(), 0), used(sg, 0);
+        for (int w = 0; w < pe->waves; ++w)
+            for (int g = 0; g < sg; ++g)
+                for (size_t q = 0; q < plan->queues.size(); ++q) {
+                    const PoolQueue& Q = plan->queues[q];
+                    if (taken[q] < Q.count && used[g] + Q.pages <= plan->pool_pages) {
+                        plan->seeds[(size_t)g * pe->waves + w] = PoolSeed{Q.first + taken[q], used[g]};
+                        used[g] += Q.pages;
+                        ++taken[q];
+                        break;
+                    }
+                }
+        for (size_t q = 0; q < plan->queues.size(); ++q) {
+            plan->queues[q].first += taken[q];
+            plan->queues[q].count -= taken[q];
+        }
         plan->buckets.push_back(bk);
     }
     std::vector<double> item_cost(plan->items.size(), 0.0);   // estimated cycles, aligned with items
@@ -922,6 +949,10 @@ int afps_plan_upload(afps_plan* plan, void* workspace, size_t workspace_bytes, v
         AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolTableOffset, plan->queues.data(),
                                 plan->queues.size() * sizeof(PoolQueue), hipMemcpyHostToDevice,
                                 (hipStream_t)stream));
+    if (!plan->seeds.empty())
+        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolSeedOffset, plan->seeds.data(),
+                                plan->seeds.size() * sizeof(PoolSeed), hipMemcpyHostToDevice,
+                                (hipStream_t)stream));
     AFPS_HIP(hipMemcpyAsync((char*)workspace + kItemsOffset, plan->items.data(),
                             plan->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
                             (hipStream_t)stream));
@@ -944,6 +975,7 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
     unsigned* counters = (unsigned*)workspace;
     unsigned* qtaken = (unsigned*)((char*)workspace + kPoolCounterOffset);
     const PoolQueue* queues = (const PoolQueue*)((char*)workspace + kPoolTableOffset);
+    const PoolSeed* seeds = (const PoolSeed*)((char*)workspace + kPoolSeedOffset);
     const WorkItem* items = (const WorkItem*)((char*)workspace + kItemsOffset);
     int nb = (int)plan->buckets.size();
     int reset_words = kResetWords;
@@ -955,9 +987,10 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
         if (bk.pool) {
             int nq = (int)plan->queues.size();
             int pages = plan->pool_pages;
+            int seed_groups = (int)plan->seeds.size() / (bk.block / 64);
             unsigned spin = g_spin_limit;
             void* args[] = {(void*)&xyz_all, (void*)&out_all, (void*)&items, (void*)&queues,
-                            &nq, (void*)&qtaken, &pages, &spin};
+                            &nq, (void*)&qtaken, (void*)&seeds, &seed_groups, &pages, &spin};
             AFPS_HIP(hipLaunchKernel(bk.kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
             return AFPS_OK;
         }

@@ -9,6 +9,12 @@
 // in the largest free run of its pool, so the long sectors (the critical path
 // of the batch) start first and the short ones fill the pages left over.
 //
+// Each wave's first sector (its seed) and that sector's pages are chosen when
+// the plan is built, by the same policy played out for the moment all waves
+// start; the seeds' pages are marked used before the workgroup's start
+// barrier, so a launch begins without every wave contending for the same
+// queue counter.
+//
 // Allocation is serialised per workgroup by an LDS lock; frees are atomic
 // ANDs on the used-mask and need no lock.  Every wait (for the lock, or for
 // pages another wave of the workgroup still holds) polls at most spin_limit
@@ -75,18 +81,45 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
                                                              int32_t* __restrict__ out_all,
                                                              const WorkItem* __restrict__ items,
                                                              const PoolQueue* __restrict__ queues,
-                                                             int nq, unsigned* qtaken, int pool_pages,
+                                                             int nq, unsigned* qtaken,
+                                                             const PoolSeed* __restrict__ seeds,
+                                                             int seed_groups, int pool_pages,
                                                              unsigned spin_limit) {
+    static_assert(W <= kMaxPoolWaves, "seed table holds kMaxPoolWaves waves per workgroup");
     extern __shared__ __attribute__((aligned(16))) uint32_t pool[];
     __shared__ uint64_t used[3];
     __shared__ uint32_t lock;
     const int lane = threadIdx.x & 63;
+    const bool seeded = (int)blockIdx.x < seed_groups;
     if (threadIdx.x < 3) {
-        const int lo = 64 * (int)threadIdx.x;
-        used[threadIdx.x] = pool_pages <= lo ? ~0ull : (pool_pages >= lo + 64 ? 0ull : (~0ull << (pool_pages - lo)));
+        const int wd = (int)threadIdx.x, lo = 64 * wd;
+        uint64_t u = pool_pages <= lo ? ~0ull : (pool_pages >= lo + 64 ? 0ull : (~0ull << (pool_pages - lo)));
+        if (seeded)
+            for (int w = 0; w < W; ++w) {
+                const PoolSeed sd = seeds[blockIdx.x * W + w];
+                if (sd.item >= 0) u |= page_bits(wd, sd.page, npdu_pool_pages(items[sd.item].n));
+            }
+        used[wd] = u;
     }
     if (threadIdx.x == 0) lock = 0u;
     __syncthreads();   // the only workgroup barrier: from here on waves are independent
+
+    // ---- the wave's seed: pages already marked, no lock
+    if (seeded) {
+        const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const PoolSeed sd = seeds[blockIdx.x * W + wv];
+        if (sd.item >= 0) {
+            const WorkItem wi = items[sd.item];
+            const int p = npdu_pool_pages(wi.n);
+            run_item(xyz_all, out_all, wi, pool + sd.page * (kPoolPageBytes / 4));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // this sector's accesses are done
+            if (lane == 0)
+                for (int wd = 0; wd < 3; ++wd) {
+                    const uint64_t m = page_bits(wd, sd.page, p);
+                    if (m) __hip_atomic_fetch_and(&used[wd], ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+        }
+    }
 
     // This lane's two queues (lane, lane + 64): their page counts and sizes.
     const int q0 = lane, q1 = lane + 64;

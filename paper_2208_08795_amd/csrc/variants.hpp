@@ -77,6 +77,16 @@ static_assert(sizeof(PoolQueue) == 16, "pool queue layout");
 constexpr int kPoolPageBytes = 1024;
 constexpr int kMaxPoolPages = 160;      // pages per workgroup, at most (used-mask of 3 words)
 constexpr int kMaxPoolQueues = 128;     // two per lane in the queue scan
+// First sector of each wave, assigned when the plan is built (no queue
+// atomics at the start of a launch): the item and its first page, item -1 if
+// none.  Seeds cover workgroups below kMaxPoolSeedGroups, kMaxPoolWaves waves
+// each.
+struct PoolSeed {
+    int32_t item;
+    int32_t page;
+};
+constexpr int kMaxPoolWaves = 8;
+constexpr int kMaxPoolSeedGroups = 512;
 struct PoolEntry {
     int waves;
     const void* kernel;
