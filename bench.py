@@ -284,9 +284,10 @@ def serving(torch, rates=(50, 200, 800), frames_npdu=160, frames_fps=24, pool=48
     return res
 
 
-def counter_traffic():
-    """HBM bytes per launch of the NPDU step from the committed FETCH_SIZE /
-    WRITE_SIZE runs, or None when the kernel sources changed since."""
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` (the NPDU step) from the committed
+    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel sources changed
+    since or that kernel was not profiled."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pooled_npdu_kernel_batch256_traffic.json")
     if not os.path.exists(path):
@@ -296,7 +297,8 @@ def counter_traffic():
     src = "".join(open(os.path.join(ROOT, s)).read() for s in rec["sources"])
     if hashlib.sha256(src.encode()).hexdigest() != rec["source_sha256"]:
         return None
-    return rec["traffic_bytes_per_launch"]
+    k = rec.get("kernels", {}).get(kernel)
+    return k["traffic_bytes_per_launch"] if k else None
 
 
 def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
@@ -346,6 +348,9 @@ def main():
     ap.add_argument("--no-fps", action="store_true", help="skip the plain-FPS comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving streams")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (built-in variant rule)")
+    ap.add_argument("--occupancy", type=float, default=None,
+                    help="plan wave budget in waves per SIMD for the timed batch (skips its tuning; "
+                         "0 = the built-in rule, >= 1.5 = two pooled waves per SIMD)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -373,7 +378,10 @@ def main():
     calib2 = torch.empty_like(calib)
     calib2.copy_(calib)
 
-    if not args.no_tune:
+    tuned_occ = args.occupancy is None and not args.no_tune
+    if args.occupancy is not None:
+        binding.set_plan_occupancy(args.occupancy)
+    elif tuned_occ:
         from paper_2208_08795_amd import autotune
         log("autotuning the batch plan's wave budget")
         occ = autotune.tune_occupancy(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256, log=log)
@@ -394,8 +402,10 @@ def main():
                                   "C = N/4 (%d samples), AFPS M=8 with NPDU k=32, one persistent launch "
                                   "per step replayed from a hipGraph" % (sum(sizes), total_samples),
                       "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples}}
-    if not args.no_tune:
+    if tuned_occ:
         res["plan_occupancy_tuning"] = {"waves_per_simd_vs_ms": res_occ, "chosen": res_occ[0][0]}
+    elif args.occupancy is not None:
+        res["plan_occupancy"] = args.occupancy
     res["batch_latency"] = {"unit": "ms", "what": "per step (whole batch of 256 clouds), HIP events",
                             "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
 
@@ -406,7 +416,7 @@ def main():
     hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
     res["roofline"] = {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": VALU_PEAK_TOPS,
                        "unit": "TOPS (fp32 VALU ops)", "frac": ops / kern_s / 1e12 / VALU_PEAK_TOPS,
-                       "traffic": counter_traffic(),
+                       "traffic": counter_traffic("pooled_npdu_kernel<%d>" % plan.pool_waves),
                        "kernel": "pooled_npdu_kernel<%d>" % plan.pool_waves,
                        "algorithmic_ops_per_launch": ops, "distance_updates_per_launch": upd,
                        "hbm_bytes_per_launch": hbm_bytes,
