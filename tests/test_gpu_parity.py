@@ -170,6 +170,29 @@ def test_npdu_wide_windows(B, torch_dev, q):
                    flags=flags)
 
 
+@pytest.mark.parametrize("q", [4, 8])
+def test_npdu_large_sectors(B, torch_dev, q):
+    """Sectors whose coordinates stay in L2 (more than 8192 points), narrow
+    windows: the first sweep through untouched points and the jumps after it,
+    windows at both ends, exact ties, every point sampled, both edge readings
+    and the full first update, one and two sectors."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(1300 + q)
+    for n in (4096 * q, 4096 * q - 37, 4096 * q // 2 + 1):
+        pts = synth.lidar_scan(-(-n // 64), seed=n, n=n)
+        ties = rng.integers(0, 3, (n, 3)).astype(np.float32)
+        for p, c, k, flags, start in [(pts, 2000, 64, 0, 0), (pts, 2000, 32, 0, n - 1), (pts, 1500, 63, 2, n // 2),
+                                      (pts, 1200, 1, 0, 5), (pts, 1200, 0, 0, n - 3), (pts, 900, 2, 1, 0),
+                                      (pts, 900, 64, 3, n - 1), (ties, 1500, 64, 0, n // 3), (ties, 700, 17, 2, 0)]:
+            _check(B, torch, dev, p, c, 1, k, start, variant=(1, q), label="large-q%d" % q, flags=flags)
+    n = 4096 * q // 2 + 77
+    pts = synth.object_cloud(n, seed=q)
+    _check(B, torch, dev, pts, n, 1, 64, 0, variant=(1, q), label="large-every-point")
+    big = synth.lidar_scan(-(-(2 * n) // 64), seed=5, n=2 * n)
+    for k in (8, 33, 64):
+        _check(B, torch, dev, big, 2 * n // 8, 2, k, int(rng.integers(0, 2 * n)), label="large-m2")
+
+
 READING_FLAGS = (1, 2, 3, 4, 5, 6, 7)   # full first update, shifted windows, k counting the sample
 
 
