@@ -582,6 +582,20 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
             bi[r] = writelane(bi[r], i, blk & 63);
         });
     };
+    // Blocks b0 and b0 + 1 (the latter dropped when past the registers)
+    // take maxima g0, g1 and first positions i0, i1: in every register, the
+    // lanes of the two blocks select the new values; no branch, no lane
+    // write, so the register of a block need not be known.
+    auto set_pair = [&](int b0, uint32_t g0, uint32_t i0, uint32_t g1, uint32_t i1) {
+        const bool first = lane == (b0 & 63);
+        const uint32_t gs = first ? g0 : g1, is = first ? i0 : i1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool mine = (uint32_t)(64 * r + lane - b0) < 2u;
+            bm[r] = mine ? gs : bm[r];
+            bi[r] = mine ? is : bi[r];
+        }
+    };
     // The lowest index holding distance g: the lowest block, then its position.
     auto lowest_with = [&](uint32_t g) {
         int idx = 0;
@@ -647,8 +661,7 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
         const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
         // Block b0+1 may be the padding block (maximum 0, never the lowest
         // holder of a maximum); past the registers it is not recorded.
-        if (b0 + 1 < 64 * R) set_block(b0 + 1, g1, i1);
-        set_block(b0, g0, i0);
+        set_pair(b0, g0, i0, g1, i1);
         return max(g0, g1);
     };
 
