@@ -57,6 +57,8 @@ def load(path: str | None = None):
         lib.oracle_fps.restype = ctypes.c_int
         lib.oracle_sector.argtypes = [i32, i32, i32, i32, iptr, iptr, iptr, iptr]
         lib.oracle_sector.restype = None
+        lib.oracle_ball_query.argtypes = [fptr, i32, iptr, i32, ctypes.c_float, i32, i32, iptr, iptr]
+        lib.oracle_ball_query.restype = ctypes.c_int
         if path is None:
             _lib = lib
         return lib
@@ -114,3 +116,27 @@ def sector(n: int, c: int, m: int, s: int, lib=None):
     vals = [ctypes.c_int32() for _ in range(4)]
     lib.oracle_sector(n, c, m, s, *[ctypes.byref(v) for v in vals])
     return tuple(v.value for v in vals)
+
+
+def ball_query(points, centers, radius: float, k: int, window: int | None = None, lib=None):
+    """Grouping around the samples (the consumer the paper names, Sec. I and
+    II-A): up to ``k`` neighbours per centre with squared fp32 distance below
+    fp32(radius * radius), in increasing index order, padded with the first
+    found (the centre itself when none is); ``window`` bounds the candidates
+    to storage positions within ``window`` of the centre (None: all points).
+
+    Returns (idx int32 (C, k), count int32 (C,))."""
+    lib = lib or load()
+    p = _points(points)
+    ctr = np.ascontiguousarray(centers, dtype=np.int32)
+    c = ctr.shape[0]
+    idx = np.empty((c, k), dtype=np.int32)
+    cnt = np.empty(c, dtype=np.int32)
+    iptr = ctypes.POINTER(ctypes.c_int32)
+    rc = lib.oracle_ball_query(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.shape[0],
+                               ctr.ctypes.data_as(iptr), c, float(radius), int(k),
+                               -1 if window is None else int(window), idx.ctypes.data_as(iptr),
+                               cnt.ctypes.data_as(iptr))
+    if rc != 0:
+        raise OracleError("oracle_ball_query returned %d" % rc)
+    return idx, cnt

@@ -213,3 +213,44 @@ int oracle_fps(const float *P, int32_t n, int32_t c, int32_t start, int32_t *out
 {
     return oracle_afps(P, n, c, 1, -1, start, out, dist, evals);
 }
+
+/*
+ * Grouping around the samples: the second half of a PointNet++ set
+ * abstraction layer, which the paper names as the consumer of the samples
+ * (Sec. I, Sec. II-A) without defining it.  Readings (design notes):
+ *   - ball query: the neighbours of centre q are the points j with
+ *     squared_distance(P[j], P[q]) < r2 (fp32, the distance above; r2 =
+ *     radius * radius rounded to fp32), taken in increasing index order, at
+ *     most K of them; slots past the found ones repeat the first found, or
+ *     hold q when none was found (radius 0);
+ *   - search window (Sec. III-A: with dimensional locality, storage
+ *     neighbours approximate spatial neighbours): only j in
+ *     [q - window, q + window] are candidates; window < 0 searches the whole
+ *     cloud (the exact ball query).
+ * out_idx gets K indices per centre (centre-major), out_cnt the number found
+ * (at most K) per centre.
+ */
+int oracle_ball_query(const float *P, int32_t n, const int32_t *centers, int32_t c, float radius,
+                      int32_t K, int32_t window, int32_t *out_idx, int32_t *out_cnt)
+{
+    if (!P || !centers || !out_idx || !out_cnt) return ORACLE_ERR_NULL;
+    if (n < 1 || c < 0 || K < 1 || !(radius >= 0.0f)) return ORACLE_ERR_ARG;
+    const float r2 = radius * radius;
+    for (int32_t q = 0; q < c; ++q) {
+        const int32_t ci = centers[q];
+        if (ci < 0 || ci >= n) return ORACLE_ERR_RANGE;
+        int32_t lo = 0, hi = n - 1;
+        if (window >= 0) {
+            lo = ci - window < 0 ? 0 : ci - window;
+            hi = ci > n - 1 - window ? n - 1 : ci + window;
+        }
+        int32_t *row = out_idx + (int64_t)q * K;
+        int32_t found = 0;
+        for (int32_t j = lo; j <= hi && found < K; ++j)
+            if (squared_distance(P + 3 * (int64_t)j, P + 3 * (int64_t)ci) < r2) row[found++] = j;
+        const int32_t fill = found > 0 ? row[0] : ci;
+        for (int32_t l = found; l < K; ++l) row[l] = fill;
+        out_cnt[q] = found;
+    }
+    return ORACLE_OK;
+}
