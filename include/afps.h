@@ -287,6 +287,31 @@ int afps_check_points(const float *xyz, int64_t n, void *stream);
  */
 int afps_set_checking(int32_t on);
 
+/* ------------------------------------------------------------- grouping */
+
+/*
+ * Grouping around the samples: the ball query of a PointNet++ set
+ * abstraction layer, which the paper names as the consumer of the samples
+ * (Sec. I, Sec. II-A) without defining it; the readings are those of the
+ * oracle.  For each centre q (an index into the cloud, typically a sample
+ * returned by the calls above), the first k points j in increasing index
+ * order with squared distance ((dx*dx + dy*dy) + dz*dz, dx = x_j - x_q, fp32,
+ * no fused multiply-add) below r2 = radius * radius (rounded to fp32); the
+ * slots past the found ones repeat the first found, or hold q when none was
+ * found (radius 0).  window >= 0 bounds the candidates to storage positions
+ * [q - window, q + window] (with dimensional locality, Sec. III-A, storage
+ * neighbours approximate spatial ones); window < 0 searches the whole cloud.
+ *   xyz      DEVICE, n x 3 fp32 row-major, n >= 1
+ *   centers  DEVICE, c int32 indices; an index outside [0, n) yields -1 in
+ *            all k slots and in its count (nothing outside the cloud is read)
+ *   out_idx  DEVICE, c x k int32 (centre-major), fully written
+ *   out_cnt  DEVICE, c int32 neighbours found (at most k), or NULL
+ * Requires c >= 0, k >= 1 and radius >= 0 (AFPS_ERR_ARG otherwise, nothing
+ * launched).  One kernel launch (capturable); asynchronous on `stream`.
+ */
+int afps_ball_query(const float *xyz, int32_t n, const int32_t *centers, int32_t c, float radius,
+                    int32_t k, int32_t window, int32_t *out_idx, int32_t *out_cnt, void *stream);
+
 /* --------------------------------------------------------------- status */
 
 const char *afps_status_string(int status);  /* static string */

@@ -77,6 +77,7 @@ def lib():
             "afps_bin_workspace_bytes": ([i32, i32], ctypes.c_size_t),
             "afps_bin_points": ([vp, i32, i32, i32, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
             "afps_set_checking": ([i32], ctypes.c_int),
+            "afps_ball_query": ([vp, i32, vp, i32, ctypes.c_float, i32, i32, vp, vp, vp], ctypes.c_int),
             "afps_set_plan_occupancy": ([ctypes.c_float], ctypes.c_int),
             "afps_status_string": ([ctypes.c_int], ctypes.c_char_p),
             "afps_last_error": ([], ctypes.c_char_p),
@@ -294,6 +295,30 @@ def bin_points(xyz, axis: int, bins: int, with_points: bool = True, stream=None)
                                  ctypes.c_void_p(out.data_ptr()) if out is not None else None,
                                  ctypes.c_void_p(ws.data_ptr()), need, _stream_handle(stream)))
     return perm[:n], out
+
+
+def ball_query(xyz, centers, radius: float, k: int, window: int | None = None, out=None, counts=None,
+               stream=None):
+    """Grouping around the samples (ball query; see afps_ball_query): returns
+    (idx int32 (C, k), count int32 (C,)) for the int32 centre indices
+    ``centers``; ``window`` bounds the candidates to storage positions within
+    ``window`` of each centre (None: the whole cloud)."""
+    torch = _torch()
+    _check_points(xyz)
+    if centers.dtype != torch.int32 or not centers.is_contiguous() or centers.device != xyz.device:
+        raise ValueError("centers must be a contiguous int32 tensor on the points' device")
+    c = centers.shape[0]
+    if out is None:
+        out = torch.empty((c, k), dtype=torch.int32, device=xyz.device)
+    if counts is None:
+        counts = torch.empty(c, dtype=torch.int32, device=xyz.device)
+    if out.shape != (c, k) or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 (C, k) tensor")
+    _check(lib().afps_ball_query(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], ctypes.c_void_p(centers.data_ptr()),
+                                 c, float(radius), int(k), -1 if window is None else int(window),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(counts.data_ptr()),
+                                 _stream_handle(stream)))
+    return out, counts
 
 
 def set_checking(on: bool):

@@ -29,6 +29,7 @@ def _units():
     units += [("kernels_npdu.hip", "kernels_npdu.o", []), ("kernels_pool.hip", "kernels_pool.o", []),
               ("fps_grid.hip", "fps_grid.o", []), ("check.hip", "check.o", []),
               ("binning.hip", "binning.o", []),
+              ("group.hip", "group.o", []),
               ("afps_api.cpp", "afps_api.o", ["-x", "hip"])]
     return units
 

@@ -589,6 +589,28 @@ int afps_bin_points(const float* xyz, int32_t n, int32_t axis, int32_t bins, int
     return AFPS_OK;
 }
 
+int afps_ball_query(const float* xyz, int32_t n, const int32_t* centers, int32_t c, float radius, int32_t k,
+                    int32_t window, int32_t* out_idx, int32_t* out_cnt, void* stream) {
+    if (!xyz || !centers || !out_idx) return fail(AFPS_ERR_NULL, "xyz, centers and out_idx must be non-null");
+    if (n < 1) return fail(AFPS_ERR_ARG, "n must be >= 1");
+    if (c < 0) return fail(AFPS_ERR_ARG, "c must be >= 0");
+    if (k < 1) return fail(AFPS_ERR_ARG, "k must be >= 1");
+    if (!(radius >= 0.0f)) return fail(AFPS_ERR_ARG, "radius must be >= 0");
+    if (c == 0) return AFPS_OK;
+    int rc = maybe_check_cloud(xyz, n, stream);
+    if (rc) return rc;
+    const float r2 = radius * radius;   // fp32, as the oracle rounds it
+    uint32_t r2_bits;
+    std::memcpy(&r2_bits, &r2, sizeof(r2_bits));
+    DeviceState* ds = nullptr;
+    if ((rc = device_state(&ds))) return rc;
+    const int waves = 4;   // one centre per wave, four waves per workgroup
+    const int grid = (int)std::min<int64_t>(((int64_t)c + waves - 1) / waves, (int64_t)ds->cu_count * 16);
+    void* args[] = {(void*)&xyz, &n, (void*)&centers, &c, &r2_bits, &k, &window, &out_idx, &out_cnt};
+    AFPS_HIP(hipLaunchKernel(ball_query_kernel_ptr(), dim3(grid), dim3(64 * waves), args, 0, (hipStream_t)stream));
+    return AFPS_OK;
+}
+
 int afps_check_points(const float* xyz, int64_t n, void* stream) {
     if (!xyz) return fail(AFPS_ERR_NULL, "xyz must be non-null");
     if (n < 0 || n > INT32_MAX) return fail(AFPS_ERR_ARG, "n must be in [0, 2^31-1]");

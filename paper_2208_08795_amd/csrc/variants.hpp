@@ -123,6 +123,9 @@ struct CheckResult {
 static_assert(sizeof(CheckResult) == 32, "check result layout");
 const void* check_points_kernel();
 
+// Grouping around the samples (group.hip): the ball-query kernel.
+const void* ball_query_kernel_ptr();
+
 // Binning along one axis (binning.hip): a stable counting sort by bin.
 constexpr int kBinChunk = 1024;   // points per histogram chunk (one scatter wave each)
 constexpr int kMaxBins = 8192;    // bins counted in LDS

@@ -83,6 +83,15 @@ def test_host_validation_without_gpu(L):
     assert L.afps_tune_set(100, 1, 1, 1) == -2   # NPDU is not tuned
     assert L.afps_tune_set(100, 0, 1, 1) == -2   # 64 points: too small for 100
     assert L.afps_max_sector_points() == 32768
+    # grouping: arguments checked on the host; no centres launches nothing
+    assert L.afps_ball_query(None, 10, dummy, 4, 1.0, 8, -1, dummy, None, None) == -1
+    assert L.afps_ball_query(dummy, 10, None, 4, 1.0, 8, -1, dummy, None, None) == -1
+    assert L.afps_ball_query(dummy, 0, dummy, 4, 1.0, 8, -1, dummy, None, None) == -2
+    assert L.afps_ball_query(dummy, 10, dummy, 4, 1.0, 0, -1, dummy, None, None) == -2
+    assert L.afps_ball_query(dummy, 10, dummy, 4, -1.0, 8, -1, dummy, None, None) == -2
+    assert L.afps_ball_query(dummy, 10, dummy, 4, float("nan"), 8, -1, dummy, None, None) == -2
+    assert L.afps_ball_query(dummy, 10, dummy, -1, 1.0, 8, -1, dummy, None, None) == -2
+    assert L.afps_ball_query(dummy, 10, dummy, 0, 1.0, 8, -1, dummy, None, None) == 0
 
 
 def test_descriptor_layout():
