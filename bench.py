@@ -199,6 +199,45 @@ def object_sweep(torch, binding, synth, stream, reps=10):
     return rows, readings
 
 
+def grouping(torch, binding, synth, stream, reps=10):
+    """Grouping around the samples (ball query, k = 32): the LiDAR frame of
+    32768 points around its 8192 AFPS-NPDU samples (M = 16, k = 64) within
+    1 m, and the 8192-point object cloud around its 2048 samples (M = 8,
+    k = 32) within 0.1; the exact query and storage windows.  Per window:
+    time (ms, median of HIP events), mean neighbours found (at most 32), and
+    their total relative to the exact query's (every neighbour a window finds
+    lies within the radius; a window can only find fewer)."""
+    res = {}
+    for name, pts, c, m, k, radius in [("lidar_n32768_c8192", synth.lidar_scan(512, 0), 8192, 16, 64, 1.0),
+                                       ("object_n8192_c2048", synth.object_cloud(8192, 0), 2048, 8, 32, 0.1)]:
+        xyz = torch.from_numpy(pts).cuda()
+        centers = binding.afps_npdu(xyz, c, m, k, 0, stream=stream)
+        rows = []
+        exact_cnt = None
+        for window in (None, 1024, 256, 64):
+            idx = torch.empty((c, 32), dtype=torch.int32, device="cuda")
+            cnt = torch.empty(c, dtype=torch.int32, device="cuda")
+            run = lambda: binding.ball_query(xyz, centers, radius, 32, window, out=idx, counts=cnt, stream=stream)
+            run()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                run()
+                b.record(stream)
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            cn = cnt.cpu().numpy()
+            if window is None:
+                exact_cnt = cn
+            rows.append({"window": window, "ms": round(float(np.median(ts)), 4),
+                         "mean_found": round(float(cn.mean()), 2),
+                         "found_vs_exact": round(float(cn.sum() / max(1, exact_cnt.sum())), 4)})
+        res[name] = {"radius": radius, "k": 32, "centres": "AFPS-NPDU M=%d k=%d, %d samples" % (m, k, c), "rows": rows}
+    return res
+
+
 def sortedness(torch, binding, synth, stream, reps=10):
     """Coverage radius of AFPS relative to plain FPS on the same points stored
     in different orders (the paper's Table II setting, with the coverage radius
@@ -467,6 +506,7 @@ def main():
         res["cycles_per_iteration"]["note"] = "call time x 2.4 GHz / iterations of the longest sector (launch included)"
         res["object_n8192_c2048_sweep"], res["npdu_readings"] = object_sweep(torch, binding, synth, stream)
         res["sortedness"] = sortedness(torch, binding, synth, stream)
+        res["grouping_ball_query"] = grouping(torch, binding, synth, stream)
 
     if not args.no_serve:
         res["serving"] = serving(torch)
