@@ -110,13 +110,6 @@ __device__ __forceinline__ void wave_max2(uint32_t a, uint32_t b, uint32_t& ma, 
     ma = readlane(a, 63);
     mb = readlane(b, 63);
 }
-// Candidate (distance bits, index) `g, i` replaces (gb, ib) if it is larger,
-// or equal with a lower index.  Branch-free selects.
-__device__ __forceinline__ void take_better(uint32_t g, uint32_t i, uint32_t& gb, uint32_t& ib) {
-    const bool t = g > gb || (g == gb && i < ib);
-    gb = t ? g : gb;
-    ib = t ? i : ib;
-}
 // v_writelane_b32 (clang declares no builtin for it): `old` with lane `lane`
 // (wave-uniform) replaced by the wave-uniform `value`.
 extern "C" __device__ int afps_llvm_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane");
