@@ -789,11 +789,13 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     plan->items.reserve(staged.size());
     if (!npdu.empty()) {
         Bucket bk{nullptr, 0, 0, 0, 0, 0, 0.0, 0.0, true};
+        std::vector<double> npdu_cost;   // estimated cycles, aligned with the items
         for (const auto& q : qorder) {
             const int first = (int)plan->items.size();
             for (int i = 0; i < q.second.second; ++i) {
                 const Staged& st = npdu[q.second.first + i];
                 plan->items.push_back(st.item);
+                npdu_cost.push_back(st.cost);
                 bk.cost += st.cost;
                 bk.longest = std::max(bk.longest, st.cost);
             }
@@ -822,16 +824,23 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         // workgroup's pages), so that a launch starts without a rush of every
         // wave on the same queue counter.  A workgroup's seeds sit in
         // consecutive pages from page 0; the seeded sectors are the front of
-        // their queues, which then start after them.
+        // their queues, which then start after them.  Seeds after the first
+        // round whose estimated cost leaves room before the plan's longest
+        // item wait one sleep period before loading: the first round (the
+        // longest sectors) then loads with less competition for bandwidth,
+        // and the wait cannot lengthen the launch by the cost model.
         const int sg = std::min(bk.grid, kMaxPoolSeedGroups);
-        plan->seeds.assign((size_t)sg * pe->waves, PoolSeed{-1, 0});
+        plan->seeds.assign((size_t)sg * pe->waves, PoolSeed{-1, 0, 0});
         std::vector<int> taken(plan->queues.size(), 0), used(sg, 0);
         for (int w = 0; w < pe->waves; ++w)
             for (int g = 0; g < sg; ++g)
                 for (size_t q = 0; q < plan->queues.size(); ++q) {
                     const PoolQueue& Q = plan->queues[q];
                     if (taken[q] < Q.count && used[g] + Q.pages <= plan->pool_pages) {
-                        plan->seeds[(size_t)g * pe->waves + w] = PoolSeed{Q.first + taken[q], used[g]};
+                        const int item = Q.first + taken[q];
+                        const bool slack = w > 0 && npdu_cost[item] + kSeedSleepCycles <= bk.longest;
+                        plan->seeds[(size_t)g * pe->waves + w] =
+                            PoolSeed{item, (int16_t)used[g], (int16_t)(slack ? 1 : 0)};
                         used[g] += Q.pages;
                         ++taken[q];
                         break;

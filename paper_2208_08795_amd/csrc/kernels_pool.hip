@@ -13,7 +13,9 @@
 // the plan is built, by the same policy played out for the moment all waves
 // start; the seeds' pages are marked used before the workgroup's start
 // barrier, so a launch begins without every wave contending for the same
-// queue counter.
+// queue counter.  A seed with slack before the plan's longest sector would
+// end waits a few sleep periods first, so that the longest sectors load their
+// points with less competition for memory bandwidth.
 //
 // Allocation is serialised per workgroup by an LDS lock; frees are atomic
 // ANDs on the used-mask and need no lock.  Every wait (for the lock, or for
@@ -109,6 +111,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
         const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
         const PoolSeed sd = seeds[blockIdx.x * W + wv];
         if (sd.item >= 0) {
+            for (int z = 0; z < sd.sleeps; ++z) __builtin_amdgcn_s_sleep(127);   // kSeedSleepCycles each
             const WorkItem wi = items[sd.item];
             const int p = npdu_pool_pages(wi.n);
             run_item(xyz_all, out_all, wi, pool + sd.page * (kPoolPageBytes / 4));

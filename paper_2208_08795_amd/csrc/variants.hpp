@@ -78,13 +78,17 @@ constexpr int kPoolPageBytes = 1024;
 constexpr int kMaxPoolPages = 160;      // pages per workgroup, at most (used-mask of 3 words)
 constexpr int kMaxPoolQueues = 128;     // two per lane in the queue scan
 // First sector of each wave, assigned when the plan is built (no queue
-// atomics at the start of a launch): the item and its first page, item -1 if
-// none.  Seeds cover workgroups below kMaxPoolSeedGroups, kMaxPoolWaves waves
-// each.
+// atomics at the start of a launch): the item, its first page and how many
+// sleep periods (kSeedSleepCycles each) the wave waits before loading it;
+// item -1 if none.  Seeds cover workgroups below kMaxPoolSeedGroups,
+// kMaxPoolWaves waves each.
 struct PoolSeed {
     int32_t item;
-    int32_t page;
+    int16_t page;
+    int16_t sleeps;
 };
+static_assert(sizeof(PoolSeed) == 8, "pool seed layout");
+constexpr int kSeedSleepCycles = 127 * 64;   // one s_sleep(127)
 constexpr int kMaxPoolWaves = 8;
 constexpr int kMaxPoolSeedGroups = 512;
 struct PoolEntry {
