@@ -1,4 +1,5 @@
-"""CPU oracle for FPS / AFPS / NPDU-AFPS (Li et al., arXiv 2208.08795).
+"""CPU oracle for FPS / AFPS / NPDU-AFPS (Li et al., arXiv 2208.08795) and the
+grouping around the samples (ball query).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark are the only callers.  The GPU library never imports this

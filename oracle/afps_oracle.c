@@ -1,7 +1,8 @@
 /*
  * CPU oracle for farthest point sampling (FPS), adjustable FPS (AFPS) and
  * nearest-point distance updating (NPDU) -- Li et al., "An Adjustable Farthest
- * Point Sampling Method for Approximately-sorted Point Cloud Data".
+ * Point Sampling Method for Approximately-sorted Point Cloud Data" -- and for
+ * the grouping around the samples (ball query, at the end of this file).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
  * baseline leg of the benchmark may load this file's library.  The GPU library
