@@ -95,3 +95,40 @@ def test_lidar_frame_around_its_samples(env):
     centers = samples.cpu().numpy()
     for window in (None, 1024, 256, 64):
         _check(env, pts, centers, 1.0, 32, window, "lidar")
+
+
+def test_sampling_binning_grouping_in_one_graph(env):
+    """The single-cloud sampler, the binning and the ball query are kernel
+    launches only: captured together in one graph, every replay (with eager
+    work in between) equals the eager results."""
+    B, torch, dev = env
+    pts = synth.lidar_scan(512, 1)
+    xyz = torch.from_numpy(pts).to(dev)
+
+    def pipeline():
+        samples = B.afps_npdu(xyz, 8192, 16, 64, 0)
+        perm, binned = B.bin_points(xyz, 0, 64)
+        idx, cnt = B.ball_query(xyz, samples, 1.0, 32, 256)
+        return samples, perm, binned, idx, cnt
+
+    eager = [t.clone() for t in pipeline()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):          # warm-up on the capture stream
+        pipeline()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        static = pipeline()
+    for r in range(3):
+        for t in static:
+            t.fill_(-7)
+        graph.replay()
+        torch.cuda.synchronize()
+        for got, want in zip(static, eager):
+            assert torch.equal(got, want), "replay %d" % r
+        torch.zeros(1000, device=dev).sum().item()   # eager work between replays
+    want_idx, want_cnt = oracle.ball_query(pts, eager[0].cpu().numpy(), 1.0, 32, 256)
+    assert np.array_equal(eager[3].cpu().numpy(), want_idx) and np.array_equal(eager[4].cpu().numpy(), want_cnt)
