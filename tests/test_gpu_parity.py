@@ -152,6 +152,26 @@ def test_npdu_narrow_window_edges(B, torch_dev):
             _check(B, torch, dev, pts, n, 1, k, n - 1, label="narrow-small")
 
 
+def test_npdu_windows_up_to_32(B, torch_dev):
+    """k <= 32 on sectors up to 4096 points: sizes around 32- and 64-point
+    boundaries, windows in the last block and at both ends, k = 0 to 32,
+    every reading, ties, every point sampled, several sectors."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(88)
+    for n in (1, 2, 31, 32, 33, 63, 64, 65, 95, 96, 97, 2047, 4063, 4064, 4065, 4095, 4096):
+        pts = synth.object_cloud(n, seed=n) if n > 8 else rng.random((n, 3), dtype=np.float32)
+        for k, flags, start in [(0, 0, 0), (1, 0, n - 1), (2, 2, n // 2), (31, 0, n - 1), (32, 0, 0),
+                                (32, 1, n // 3), (17, 3, n - 1), (32, 2, n - 2 if n > 1 else 0)]:
+            _check(B, torch, dev, pts, n if n <= 1024 else 1024, 1, k, start, variant=(1, 1),
+                   label="k32-%d" % n, flags=flags)
+    ties = rng.integers(0, 3, (4096, 3)).astype(np.float32)
+    for k in (8, 32):
+        _check(B, torch, dev, ties, 4096, 1, k, 4095, variant=(1, 1), label="k32-ties")
+    cloud = synth.object_cloud(20000, seed=3)
+    for m, k in [(5, 32), (8, 16), (16, 1)]:
+        _check(B, torch, dev, cloud, 20000 // 4, m, k, 12345, label="k32-sectors")
+
+
 @pytest.mark.parametrize("q", [1, 2, 4, 8])
 def test_npdu_wide_windows(B, torch_dev, q):
     """Windows wider than two blocks (re-reduced two blocks at a time): an
