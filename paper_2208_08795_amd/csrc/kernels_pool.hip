@@ -114,7 +114,12 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
             for (int z = 0; z < sd.sleeps; ++z) __builtin_amdgcn_s_sleep(127);   // kSeedSleepCycles each
             const WorkItem wi = items[sd.item];
             const int p = npdu_pool_pages(wi.n);
+            // Wave 0's seed is its workgroup's longest sector (the first round
+            // of seeds takes the longest sectors): its instructions go first
+            // when a SIMD has another wave ready too.
+            if (wv == 0) __builtin_amdgcn_s_setprio(3);
             run_item(xyz_all, out_all, wi, pool + sd.page * (kPoolPageBytes / 4));
+            if (wv == 0) __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // this sector's accesses are done
             if (lane == 0)
                 for (int wd = 0; wd < 3; ++wd) {
