@@ -48,6 +48,11 @@ struct alignas(16) Candidate {
     uint32_t pad[3];
 };
 
+// Word 3 of a gfx9 buffer resource for raw (unswizzled, stride 0) 32-bit
+// loads: data format 32, everything else zero.  Out-of-range reads return 0.
+constexpr int kBufferWord3 = 0x00020000;
+typedef uint32_t v3u32 __attribute__((ext_vector_type(3)));
+
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
@@ -507,9 +512,10 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
 
 // NPDU on sectors of up to 4096 R points, any window: the loop of
 // sample_sector_npdu_narrow with R registers of block maxima (block 64 r + l
-// in lane l of register r; a block's register is chosen by a scalar binary
-// search, so every register index is a constant), the window's blocks
-// re-reduced two at a time, and, for sectors too large for 16 bytes per point
+// in lane l of register r; a window block's maximum goes in by a lane select
+// in every register and the block holding the new maximum is found by halving
+// the register set, so every register index is a constant), the window's
+// blocks re-reduced two at a time, and, for sectors too large for 16 bytes per point
 // of LDS (XYZ_IN_LDS = false), only D in LDS and the coordinates read from
 // global memory (L2).
 template <int R, bool XYZ_IN_LDS, bool SHIFT>
@@ -518,6 +524,15 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
                                                           int32_t* __restrict__ out, uint32_t* lds,
                                                           bool first_full) {
     static_assert(R >= 1 && R <= 8 && (R & (R - 1)) == 0, "R is 1, 2, 4 or 8 block registers");
+    // Coordinates read from global memory (XYZ_IN_LDS = false) go through a
+    // buffer resource bounded to the sector's 12 n bytes: a block's two loads
+    // take one offset add on the fixed per-lane 12 lane, and a point past the
+    // sector (in the padding block) reads as zeros instead of needing a clamp.
+    // The whole offset is in the vector offset and the immediate, both covered
+    // by the range check; a 12-byte record is either wholly inside or outside.
+    const __amdgpu_buffer_rsrc_t xyz_rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xyz), (short)0, 12 * n, kBufferWord3);
+    const int lane12 = 12 * (int)(threadIdx.x & 63);
     constexpr int kWords = XYZ_IN_LDS ? 4 : 1;   // LDS words per point: {D, x, y, z} or D
     const int lane = threadIdx.x & 63;
     const int nb = (n + 63) >> 6;
@@ -671,9 +686,12 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
         } else {
             a_d = rec[j0];
             b_d = rec[j1];
-            const int ja = min(j0, n - 1), jb = min(j1, n - 1);   // padding points read a real one
-            ax = xyz[3 * ja]; ay = xyz[3 * ja + 1]; az = xyz[3 * ja + 2];
-            bx = xyz[3 * jb]; by = xyz[3 * jb + 1]; bz = xyz[3 * jb + 2];
+            // block b0 + 1 at immediate offset +768 bytes; padding points read zeros
+            const int off = 768 * b0 + lane12;
+            const v3u32 A = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off, 0, 0);
+            const v3u32 B = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off + 768, 0, 0);
+            ax = __uint_as_float(A.x); ay = __uint_as_float(A.y); az = __uint_as_float(A.z);
+            bx = __uint_as_float(B.x); by = __uint_as_float(B.y); bz = __uint_as_float(B.z);
         }
         const uint32_t e0 = min(a_d, sq_dist_bits(ax, ay, az, px, py, pz));
         const uint32_t e1 = min(b_d, sq_dist_bits(bx, by, bz, px, py, pz));
@@ -700,9 +718,12 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
             py = __uint_as_float(rec[4 * cur + 2]);
             pz = __uint_as_float(rec[4 * cur + 3]);
         } else {
-            px = xyz[3 * cur];
-            py = xyz[3 * cur + 1];
-            pz = xyz[3 * cur + 2];
+            // a 32-bit byte offset: one scalar load with an offset register
+            const float* const p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(xyz) +
+                                                                  (uint32_t)(12 * cur));
+            px = p[0];
+            py = p[1];
+            pz = p[2];
         }
         int lo, hi;
         if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
