@@ -327,6 +327,24 @@ def test_batched_uneven_npdu_and_graph(B, torch_dev):
                 graph_replays=3)
 
 
+def test_batched_large_sectors_in_the_pool(B, torch_dev):
+    """NPDU sectors of every block-register count in one pooled launch: up to
+    4096 points (coordinates in LDS), up to 8192, and sectors whose
+    coordinates stay in L2 (up to 16 384 and 32 768 points), ragged sizes,
+    windows inside two blocks and wider, starts at both ends, the alternative
+    readings, graph replays."""
+    torch, dev = torch_dev
+    sizes = [32768, 20001, 16384, 12345, 9000, 8192, 5000, 3001, 32700, 16383]
+    ms = [1, 1, 1, 1, 2, 1, 1, 1, 2, 3]
+    ks = [64, 17, 200, 64, 33, 130, 64, 80, 8, 64]
+    cs = [900, 700, 500, 800, 600, 400, 700, 300, 1000, 600]
+    starts = [0, 20000, 5, 12344, 8999, 0, 4000, 3000, 16000, 1]
+    flags = [0, 0, 0, 2, 0, 1, 3, 0, 0, 2]
+    clouds = [synth.lidar_scan(-(-n // 64), seed=i, n=n) if i % 2 == 0 else synth.object_cloud(n, seed=i)
+              for i, n in enumerate(sizes)]
+    _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=2, flags=flags)
+
+
 @pytest.mark.parametrize("occupancy", [0.0, 1.0, 2.0, 4.0])
 def test_batch_of_256_every_cloud(B, torch_dev, occupancy):
     """The timed batch at its full size (256 object clouds, N log-uniform in
