@@ -214,17 +214,19 @@ class BatchPlan:
                                       self.workspace.numel(), _stream_handle(stream)))
         self._uploaded = True
 
-    def _args(self, xyz_all, out_all):
+    def _args(self, xyz_all, out_all, stream):
         _check_points(xyz_all)
         if xyz_all.shape[0] < self.total_points:
             raise ValueError("xyz_all holds fewer points than the plan's clouds")
         out_all = _out(xyz_all, self.total_samples, out_all)
         if not self._uploaded:
-            self.upload()
+            # on the launch stream: a stream that does not wait for the current
+            # one would otherwise read the workspace before the copy lands
+            self.upload(stream)
         return out_all
 
     def launch(self, xyz_all, out_all=None, stream=None, graph=False):
-        out_all = self._args(xyz_all, out_all)
+        out_all = self._args(xyz_all, out_all, stream)
         f = lib().afps_plan_graph_launch if graph else lib().afps_plan_launch
         _check(f(self._plan, ctypes.c_void_p(xyz_all.data_ptr()), ctypes.c_void_p(out_all.data_ptr()),
                  ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(stream)))

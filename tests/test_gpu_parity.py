@@ -345,6 +345,31 @@ def test_batched_large_sectors_in_the_pool(B, torch_dev):
     _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=2, flags=flags)
 
 
+def test_plan_first_launched_on_a_side_stream(B, torch_dev):
+    """Two plans of the same clouds, the first replayed on the current stream
+    (plain FPS, several milliseconds), the second first launched from a graph
+    on a side stream that does not wait for the current one: its workspace
+    upload is ordered on the side stream, so both results are exact."""
+    torch, dev = torch_dev
+    clouds = [synth.object_cloud(n, seed=n) for n in (32768, 3000, 1024)]
+    sizes, cs = [len(p) for p in clouds], [4096, 750, 256]
+    xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    print("side-stream plans sizes=%s" % sizes, flush=True)
+    busy = B.BatchPlan(sizes, cs, [1] * 3, [None] * 3, [0] * 3, device=dev)
+    late = B.BatchPlan(sizes, cs, [1] * 3, [None] * 3, [0] * 3, device=dev)
+    side = torch.cuda.Stream(device=dev)
+    out_busy = busy.launch(xyz, graph=True)
+    out_late = torch.empty(late.total_samples, dtype=torch.int32, device=dev)
+    late.launch(xyz, out_all=out_late, stream=side, graph=True)
+    torch.cuda.synchronize()
+    for out in (out_busy, out_late):
+        got = out.cpu().numpy()
+        for i, p in enumerate(clouds):
+            assert np.array_equal(got[busy.offsets[i]:busy.offsets[i] + cs[i]], oracle.afps(p, cs[i], 1, None, 0)), i
+    busy.close()
+    late.close()
+
+
 @pytest.mark.parametrize("occupancy", [0.0, 1.0, 2.0, 4.0])
 def test_batch_of_256_every_cloud(B, torch_dev, occupancy):
     """The timed batch at its full size (256 object clouds, N log-uniform in
