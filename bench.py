@@ -43,22 +43,43 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def time_plan(torch, plan, xyz_all, out, steps, warmup, stream):
-    """Warm up, then time exactly `steps` graph launches: wall clock between two
-    synchronisations, plus HIP events around every step on the launch stream."""
-    for _ in range(warmup):
-        plan.launch(xyz_all, out_all=out, graph=True, stream=stream)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+def time_steps(torch, plans, xyz_all, outs, steps, warmup, streams):
+    """Warm up, then time exactly `steps` graph launches, nothing else between
+    the two synchronisations.  Step i runs on stream i mod S with plan and
+    output i mod S (each plan has its own workspace), so a step starts on the
+    compute units the previous one has already finished with; every stream's
+    output is checked against the first afterwards.  Returns (wall seconds,
+    warm-up steps done)."""
+    S = len(plans)
+    done = max(warmup, S)                   # every plan's graph captured before timing
+    for i in range(done):
+        plans[i % S].launch(xyz_all, out_all=outs[i % S], graph=True, stream=streams[i % S])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for a, b in ev:
+    for i in range(steps):
+        plans[i % S].launch(xyz_all, out_all=outs[i % S], graph=True, stream=streams[i % S])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for o in outs[1:]:
+        if not torch.equal(o, outs[0]):
+            raise SystemExit("bench: the pipelined streams' outputs differ")
+    return wall, done
+
+
+def step_latency(torch, plan, xyz_all, out, reps, stream):
+    """One step's own latency: graph launches one at a time on one stream,
+    HIP events around each."""
+    plan.launch(xyz_all, out_all=out, graph=True, stream=stream)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         plan.launch(xyz_all, out_all=out, graph=True, stream=stream)
         b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return wall, [a.elapsed_time(b) for a, b in ev]
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return ms
 
 
 def time_kernel(torch, plan, xyz_all, out, reps, stream):
@@ -399,6 +420,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="streams the timed steps alternate over (each with its own plan and output)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-single", action="store_true", help="skip single-cloud latencies")
     ap.add_argument("--no-fps", action="store_true", help="skip the plain-FPS comparison")
@@ -408,6 +431,8 @@ def main():
                     help="plan wave budget in waves per SIMD for the timed batch (skips its tuning; "
                          "0 = the built-in rule, >= 1.5 = two pooled waves per SIMD)")
     args = ap.parse_args()
+    if args.streams < 1:
+        ap.error("--streams must be at least 1")
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent clouds would shard by request with no exchange)", file=sys.stderr)
@@ -442,27 +467,35 @@ def main():
         log("autotuning the batch plan's wave budget")
         occ = autotune.tune_occupancy(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256, log=log)
         res_occ = [[f, round(t, 4)] for f, t in occ]
-    plan = binding.BatchPlan(sizes, cs, [M] * 256, [K] * 256, [0] * 256, device=dev)
-    out = torch.empty(plan.total_samples, dtype=torch.int32, device=dev)
-    log("AFPS-NPDU plan: %d items, %d launch(es)" % (plan.items, plan.launches))
-    wall, ev_ms = time_plan(torch, plan, xyz_all, out, args.steps, args.warmup, stream)
+    S = args.streams
+    streams = [stream] + [torch.cuda.Stream(device=dev) for _ in range(S - 1)]
+    plans = [binding.BatchPlan(sizes, cs, [M] * 256, [K] * 256, [0] * 256, device=dev) for _ in range(S)]
+    outs = [torch.empty(plans[0].total_samples, dtype=torch.int32, device=dev) for _ in range(S)]
+    plan, out = plans[0], outs[0]
+    log("AFPS-NPDU plan: %d items, %d launch(es), %d stream(s)" % (plan.items, plan.launches, S))
+    wall, warm = time_steps(torch, plans, xyz_all, outs, args.steps, args.warmup, streams)
     ms_per_step = wall * 1e3 / args.steps
     value = total_samples / (wall / args.steps)
     out_np = out.cpu().numpy()
     log("AFPS-NPDU: %.3f ms/step, %.3e sampled pts/s" % (ms_per_step, value))
+    ev_ms = step_latency(torch, plan, xyz_all, out, max(20, args.steps), stream)
 
     res = {"metric": METRIC, "value": value, "unit": "sampled pts/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "warmup": warm, "ms_per_step": ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "256 object-like clouds, N log-uniform [1024, 32768] (%d points), "
                                   "C = N/4 (%d samples), AFPS M=8 with NPDU k=32, one persistent launch "
-                                  "per step replayed from a hipGraph" % (sum(sizes), total_samples),
-                      "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples}}
+                                  "per step replayed from a hipGraph; consecutive steps alternate over %d "
+                                  "streams, each with its own plan workspace and output"
+                                  % (sum(sizes), total_samples, S),
+                      "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples,
+                      "streams": S}}
     if tuned_occ:
         res["plan_occupancy_tuning"] = {"waves_per_simd_vs_ms": res_occ, "chosen": res_occ[0][0]}
     elif args.occupancy is not None:
         res["plan_occupancy"] = args.occupancy
-    res["batch_latency"] = {"unit": "ms", "what": "per step (whole batch of 256 clouds), HIP events",
+    res["batch_latency"] = {"unit": "ms", "what": "one step alone (whole batch of 256 clouds, graph launches "
+                                                  "one at a time on one stream), HIP events",
                             "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
 
     # Roofline of the dominant kernel (the pooled NPDU kernel is the step).
@@ -491,15 +524,17 @@ def main():
 
     if not args.no_fps:
         binding.set_plan_occupancy(0.0)      # plain FPS: grids as large as fit
-        fplan = binding.BatchPlan(sizes, cs, [1] * 256, [None] * 256, [0] * 256, device=dev)
-        fout = torch.empty(fplan.total_samples, dtype=torch.int32, device=dev)
+        fplans = [binding.BatchPlan(sizes, cs, [1] * 256, [None] * 256, [0] * 256, device=dev) for _ in range(S)]
+        fouts = [torch.empty(fplans[0].total_samples, dtype=torch.int32, device=dev) for _ in range(S)]
+        fplan, fout = fplans[0], fouts[0]
         fsteps = max(3, args.steps // 4)
-        fwall, fev = time_plan(torch, fplan, xyz_all, fout, fsteps, 1, stream)
+        fwall, _ = time_steps(torch, fplans, xyz_all, fouts, fsteps, 1, streams)
         fvalue = total_samples / (fwall / fsteps)
         fout_np = fout.cpu().numpy()
+        fev = step_latency(torch, fplan, xyz_all, fout, 3, stream)
         log("plain FPS: %.3f ms/step, %.3e sampled pts/s" % (fwall * 1e3 / fsteps, fvalue))
         res["plain_fps"] = {"value": fvalue, "unit": "sampled pts/s", "ms_per_step": fwall * 1e3 / fsteps,
-                            "steps": fsteps, "launches": fplan.launches,
+                            "steps": fsteps, "launches": fplan.launches, "streams": S,
                             "latency_p50_ms": percentile(fev, 50), "latency_p99_ms": percentile(fev, 99),
                             "afps_npdu_speedup": value / fvalue}
         # quality: coverage radius against plain FPS (fp64, 32 clouds)
@@ -511,7 +546,8 @@ def main():
             ratios.append(r_n / r_f)
         res["coverage_radius_vs_fps"] = {"mean": float(np.mean(ratios)), "max": float(np.max(ratios)),
                                          "clouds": len(ratios)}
-        fplan.close()
+        for p in fplans:
+            p.close()
 
     if not args.no_single:
         single = single_cloud_latency(torch, binding, synth, stream)
@@ -535,7 +571,8 @@ def main():
         log("oracle CPU baseline")
         res["cpu_baseline"] = cpu_baseline(clouds, cs, M, K, out_np, plan.offsets)
         log("cpu baseline: %s" % res["cpu_baseline"])
-    plan.close()
+    for p in plans:
+        p.close()
     print(json.dumps(res), flush=True)
 
 
