@@ -417,7 +417,7 @@ def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--streams", type=int, default=2,
@@ -499,14 +499,17 @@ def main():
                             "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
 
     # Roofline of the dominant kernel (the pooled NPDU kernel is the step).
+    pool_label = "pooled_npdu_kernel<%d>" % plan.pool_waves
+    if plan.pool_groups > 1:
+        pool_label += " x%d per CU" % plan.pool_groups
     ops, upd = npdu_work(sizes, cs, out_np, plan.offsets, M, K)
     kern_ms = time_kernel(torch, plan, xyz_all, out, max(10, args.steps), stream)
     kern_s = float(np.mean(kern_ms)) / 1e3
     hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
     res["roofline"] = {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": VALU_PEAK_TOPS,
                        "unit": "TOPS (fp32 VALU ops)", "frac": ops / kern_s / 1e12 / VALU_PEAK_TOPS,
-                       "traffic": counter_traffic("pooled_npdu_kernel<%d>" % plan.pool_waves),
-                       "kernel": "pooled_npdu_kernel<%d>" % plan.pool_waves,
+                       "traffic": counter_traffic(pool_label),
+                       "kernel": pool_label,
                        "algorithmic_ops_per_launch": ops, "distance_updates_per_launch": upd,
                        "hbm_bytes_per_launch": hbm_bytes,
                        "hbm_frac": hbm_bytes / kern_s / 1e9 / HBM_PEAK_GBS,

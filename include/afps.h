@@ -181,12 +181,17 @@ int32_t afps_plan_items(const afps_plan *plan);
 int32_t afps_plan_launches(const afps_plan *plan);
 
 /*
- * Waves per workgroup of the plan's pooled NPDU launch (one workgroup per CU
- * holding the CU's LDS as 1 KB pages; 4 = one wave per SIMD, 8 = two), or 0
- * if the plan has no NPDU sectors.  Chosen at plan creation from the plan's
- * longest sector and total work, or by afps_set_plan_occupancy.
+ * Waves per workgroup of the plan's pooled NPDU launch, and its workgroups per
+ * CU; both 0 if the plan has no NPDU sectors.  The launch holds each CU's LDS
+ * as 1 KB pages: one workgroup of 4 waves per CU (one wave per SIMD), one of 8
+ * (two per SIMD), or, for two per SIMD when every sector fits half of a CU's
+ * pages, two workgroups of 4 per CU with half the pages each (a launch then
+ * releases LDS half a CU at a time to launches on other streams).  Chosen at
+ * plan creation from the plan's longest sector and total work, or by
+ * afps_set_plan_occupancy.
  */
 int32_t afps_plan_pool_waves(const afps_plan *plan);
+int32_t afps_plan_pool_groups_per_cu(const afps_plan *plan);
 
 void afps_plan_destroy(afps_plan *plan);
 

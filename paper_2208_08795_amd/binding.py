@@ -66,6 +66,7 @@ def lib():
             "afps_plan_items": ([vp], i32),
             "afps_plan_launches": ([vp], i32),
             "afps_plan_pool_waves": ([vp], i32),
+            "afps_plan_pool_groups_per_cu": ([vp], i32),
             "afps_plan_destroy": ([vp], None),
             "afps_batched_workspace_bytes": ([vp, i32], sz),
             "afps_batched": ([vp, vp, i32, vp, vp, sz, vp], ctypes.c_int),
@@ -204,7 +205,8 @@ class BatchPlan:
         self.workspace_bytes = int(lib().afps_plan_workspace_bytes(h))
         self.items = int(lib().afps_plan_items(h))
         self.launches = int(lib().afps_plan_launches(h))
-        self.pool_waves = int(lib().afps_plan_pool_waves(h))   # waves per CU of the NPDU launch
+        self.pool_waves = int(lib().afps_plan_pool_waves(h))   # waves per workgroup of the NPDU launch
+        self.pool_groups = int(lib().afps_plan_pool_groups_per_cu(h))   # its workgroups per CU
         self.workspace = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
         self.offsets = [d.out_offset for d in self.descs]
         self._uploaded = False

@@ -668,7 +668,8 @@ struct afps_plan {
     std::vector<PoolQueue> queues;    // pool queues, highest priority first
     std::vector<PoolSeed> seeds;      // first sector of each pool wave (workgroup-major)
     std::vector<CheckSeg> clouds;     // each descriptor's points, for the optional input check
-    int pool_pages = 0;
+    int pool_pages = 0;               // LDS pages of one pooled workgroup
+    int pool_groups = 0;              // pooled workgroups per CU (1 or 2; 0 without NPDU sectors)
     size_t ws_bytes = 0;
     int device = 0;
     std::vector<hipEvent_t> events;   // fork / join events (1 + helper streams)
@@ -810,6 +811,18 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         const double span8 = std::max(1.18 * bk.longest, bk.cost / (6.8 * cus));
         int waves = span8 < span4 ? 8 : 4;
         if (g_waves_per_simd > 0.0f) waves = g_waves_per_simd < 1.5f ? 4 : 8;
+        // Two waves per SIMD run as two workgroups of four per CU, each owning
+        // half of the CU's pages, whenever every sector fits half: one launch
+        // runs as fast either way, but a launch then gives its LDS back half
+        // a CU at a time, so a launch queued behind it on another stream
+        // starts sooner.
+        int max_pages = 0;
+        for (const auto& q : plan->queues) max_pages = std::max(max_pages, q.pages);
+        plan->pool_groups = waves == 8 && max_pages <= plan->pool_pages / 2 ? 2 : 1;
+        if (plan->pool_groups == 2) {
+            waves = 4;
+            plan->pool_pages /= 2;
+        }
         const PoolEntry* pe = nullptr;
         for (const auto& v : registry().pool)
             if (v.waves == waves) pe = &v;
@@ -817,7 +830,7 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
         bk.kernel = pe->kernel;
         bk.block = 64 * pe->waves;
         bk.lds_bytes = plan->pool_pages * kPoolPageBytes;
-        bk.grid = std::min(ds->cu_count, bk.count);
+        bk.grid = std::min(plan->pool_groups * ds->cu_count, bk.count);
         // Seeds: the queue policy of the kernel played out on the host for
         // the moment every wave starts (wave w of every workgroup, then wave
         // w + 1, each taking the first queue with sectors left that fits its
@@ -966,6 +979,8 @@ int32_t afps_plan_pool_waves(const afps_plan* plan) {
         if (bk.pool) return bk.block / 64;
     return 0;
 }
+
+int32_t afps_plan_pool_groups_per_cu(const afps_plan* plan) { return plan ? plan->pool_groups : 0; }
 
 void afps_plan_destroy(afps_plan* plan) { delete plan; }
 

@@ -1,7 +1,9 @@
 // Pooled NPDU kernel (Sec. III-C sectors of a whole batch in one launch).
 //
 // One workgroup per CU takes the CU's whole LDS as a pool of 1 KB pages (64
-// sector records of 16 bytes).  Its W waves work independently: a wave
+// sector records of 16 bytes), or two take half of it each (the plan's
+// choice; pool_pages is the workgroup's share).  Its W waves work
+// independently: a wave
 // allocates exactly the pages of one sector (first fit, contiguous), samples
 // it with the one-wave NPDU sampler, frees the pages and takes the next
 // sector.  Sectors wait in priority queues, one per page count, ordered by

@@ -65,7 +65,8 @@ __host__ __device__ constexpr int npdu_lds_words(int n, bool xyz_in_lds) {
 }
 
 // Pooled NPDU kernel (kernels_pool.hip): one workgroup per CU owns the CU's
-// LDS as pages of 1 KB (64 records of 16 bytes); each of its W waves takes
+// LDS (or two own half of it each) as pages of 1 KB (64 records of 16
+// bytes); each of its W waves takes
 // sectors from priority queues and holds exactly the pages its sector needs.
 struct PoolQueue {
     int32_t first;     // items [first, first + count) of the plan, longest first

@@ -29,6 +29,9 @@ class _RecordingLib:
     def afps_plan_pool_waves(self, h):
         return 4
 
+    def afps_plan_pool_groups_per_cu(self, h):
+        return 1
+
     def afps_plan_upload(self, h, ws, nbytes, stream):
         self.calls.append(("upload", stream.value))
         return 0
