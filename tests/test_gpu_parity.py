@@ -380,9 +380,44 @@ def test_batch_of_256_every_cloud(B, torch_dev, occupancy):
     cs = [len(p) // 4 for p in clouds]
     B.set_plan_occupancy(occupancy)
     try:
-        _batch_case(B, torch, dev, clouds, cs, [8] * 256, [32] * 256, [0] * 256, graph_replays=2)
+        plan = _batch_case(B, torch, dev, clouds, cs, [8] * 256, [32] * 256, [0] * 256, graph_replays=2)
     finally:
         B.set_plan_occupancy(0.0)
+    # one wave per SIMD: one workgroup of four per CU; two per SIMD: every
+    # sector of this batch fits half a CU's pages, so two workgroups of four
+    if occupancy == 1.0:
+        assert (plan.pool_waves, plan.pool_groups) == (4, 1)
+    elif occupancy >= 2.0:
+        assert (plan.pool_waves, plan.pool_groups) == (4, 2)
+
+
+def test_pipelined_steps_on_two_streams(B, torch_dev):
+    """Consecutive steps alternating over two streams, each with its own plan
+    (split pool: two workgroups per CU) and output, several replays each in
+    flight together: every output equals the oracle."""
+    torch, dev = torch_dev
+    clouds = synth.batch_of_objects(64, seed=12, n_min=1024, n_max=32768)
+    sizes, cs = [len(p) for p in clouds], [len(p) // 4 for p in clouds]
+    xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    print("pipelined plans clouds=%d points=%d" % (len(clouds), sum(sizes)), flush=True)
+    B.set_plan_occupancy(4.0)
+    try:
+        plans = [B.BatchPlan(sizes, cs, [8] * 64, [32] * 64, [0] * 64, device=dev) for _ in range(2)]
+    finally:
+        B.set_plan_occupancy(0.0)
+    assert all(p.pool_groups == 2 for p in plans)
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream(device=dev)]
+    outs = [torch.full((plans[0].total_samples,), -7, dtype=torch.int32, device=dev) for _ in range(2)]
+    for i in range(10):
+        plans[i % 2].launch(xyz, out_all=outs[i % 2], stream=streams[i % 2], graph=i >= 2)
+    torch.cuda.synchronize()
+    want = [oracle.afps(p, c, 8, 32, 0) for p, c in zip(clouds, cs)]
+    for out in outs:
+        got = out.cpu().numpy()
+        for i, w in enumerate(want):
+            assert np.array_equal(got[plans[0].offsets[i]:plans[0].offsets[i] + cs[i]], w), i
+    for p in plans:
+        p.close()
 
 
 def test_batched_mixed_variants(B, torch_dev):
