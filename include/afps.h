@@ -151,9 +151,12 @@ size_t afps_workspace_bytes_for_items(int32_t items);
 
 /*
  * Copy the plan's tables (NPDU queues and first sectors, work items) into `workspace` (DEVICE,
- * >= the size above, 256-byte aligned) on `stream`.  Must precede
- * afps_plan_launch with that workspace; the tables stay valid until
- * overwritten.
+ * >= the size above, 256-byte aligned) on `stream`, asynchronously.  Must precede
+ * afps_plan_launch with that workspace in stream order: a launch on another
+ * stream is ordered after the copy by the caller (an event, or a stream that
+ * waits for this one); the tables stay valid until overwritten.  A plan's
+ * launches on several streams at once each need their own workspace (its
+ * queue counters are reset and consumed by every launch).
  */
 int afps_plan_upload(afps_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
 
