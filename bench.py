@@ -465,7 +465,8 @@ def main():
     elif tuned_occ:
         from paper_2208_08795_amd import autotune
         log("autotuning the batch plan's wave budget")
-        occ = autotune.tune_occupancy(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256, log=log)
+        occ = autotune.tune_occupancy(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256,
+                                      streams=args.streams, log=log)
         res_occ = [[f, round(t, 4)] for f, t in occ]
     S = args.streams
     streams = [stream] + [torch.cuda.Stream(device=dev) for _ in range(S - 1)]
@@ -491,7 +492,8 @@ def main():
                       "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples,
                       "streams": S}}
     if tuned_occ:
-        res["plan_occupancy_tuning"] = {"waves_per_simd_vs_ms": res_occ, "chosen": res_occ[0][0]}
+        res["plan_occupancy_tuning"] = {"waves_per_simd_vs_ms": res_occ, "chosen": res_occ[0][0],
+                                        "what": "ms per step, timed as the steps are (%d stream(s))" % S}
     elif args.occupancy is not None:
         res["plan_occupancy"] = args.occupancy
     res["batch_latency"] = {"unit": "ms", "what": "one step alone (whole batch of 256 clouds, graph launches "

@@ -98,23 +98,38 @@ def tune(classes=CLASSES, reps: int = 3, batch_points: int = 1 << 22, max_iters:
 
 
 def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.0, 1.0, 2.0, 4.0),
-                   reps: int = 5, install: bool = True, log=None):
+                   reps: int = 5, streams: int = 1, install: bool = True, log=None):
     """Sector-to-CU mapping of batch plans: time the batch's persistent launches
     under several wave budgets (waves per SIMD; 0 = no budget, as many
-    workgroups as fit) and keep the fastest.  Returns [(factor, ms)], best
-    first."""
+    workgroups as fit) and keep the fastest.  With streams > 1 the batch is
+    timed as it will run, consecutive graph launches alternating over that
+    many streams with a plan and output each (ms per launch over
+    20 * streams launches); otherwise one launch at a time (median of reps).
+    Returns [(factor, ms)], best first."""
     import torch
 
     from . import binding
+    dev = xyz_all.device
     res = []
     for f in factors:
         binding.set_plan_occupancy(f)
-        plan = binding.BatchPlan(sizes, cs, ms, ks, starts, device=xyz_all.device)
-        out = torch.empty(plan.total_samples, dtype=torch.int32, device=xyz_all.device)
-        plan.launch(xyz_all, out_all=out, graph=True)
-        ms_ = _time(lambda: plan.launch(xyz_all, out_all=out, graph=True), reps)
+        plans = [binding.BatchPlan(sizes, cs, ms, ks, starts, device=dev) for _ in range(streams)]
+        outs = [torch.empty(plans[0].total_samples, dtype=torch.int32, device=dev) for _ in range(streams)]
+        strs = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(device=dev) for _ in range(streams - 1)]
+        for p, o, st in zip(plans, outs, strs):
+            p.launch(xyz_all, out_all=o, graph=True, stream=st)
         torch.cuda.synchronize()
-        plan.close()
+        if streams == 1:
+            ms_ = _time(lambda: plans[0].launch(xyz_all, out_all=outs[0], graph=True), reps)
+        else:
+            n = 20 * streams
+            t0 = time.perf_counter()
+            for i in range(n):
+                plans[i % streams].launch(xyz_all, out_all=outs[i % streams], graph=True, stream=strs[i % streams])
+            torch.cuda.synchronize()
+            ms_ = (time.perf_counter() - t0) * 1e3 / n
+        for p in plans:
+            p.close()
         res.append((f, ms_))
         if log:
             log("plan occupancy %.1f waves/SIMD: %.4f ms" % (f, ms_))
