@@ -119,6 +119,18 @@ def _check_points(xyz):
         raise TypeError("xyz must be a contiguous float32 (N, 3) tensor")
 
 
+def _used_on(stream, *tensors):
+    """Tensors that the library's kernels read or write on an explicitly given
+    stream: the caching allocator must not hand their memory to another tensor
+    before that stream's queued work is done, even if the caller drops them
+    first (they were allocated on, and are freed to, the current stream)."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None and t.is_cuda:
+            t.record_stream(stream)
+
+
 def _out(xyz, c, out):
     torch = _torch()
     if out is None:
@@ -132,6 +144,7 @@ def fps(xyz, c: int, start: int = 0, out=None, stream=None):
     """Plain FPS (Algorithm 1) -> int32 indices."""
     _check_points(xyz)
     out = _out(xyz, c, out)
+    _used_on(stream, xyz, out)
     _check(lib().afps_fps_plain(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, start,
                                 ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
@@ -144,6 +157,7 @@ def afps(xyz, c: int, m: int, start: int = 0, out=None, stream=None, variant=Non
     """
     _check_points(xyz)
     out = _out(xyz, c, out)
+    _used_on(stream, xyz, out)
     if variant is None:
         rc = lib().afps_afps(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, start,
                              ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
@@ -165,6 +179,7 @@ def afps_npdu(xyz, c: int, m: int, k: int, start: int = 0, out=None, stream=None
     ``flags`` selects the alternative readings (NPDU_*)."""
     _check_points(xyz)
     out = _out(xyz, c, out)
+    _used_on(stream, xyz, out)
     if variant is None:
         rc = lib().afps_afps_npdu_ex(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], c, m, k, start, flags,
                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
@@ -212,6 +227,7 @@ class BatchPlan:
         self._uploaded = False
 
     def upload(self, stream=None):
+        _used_on(stream, self.workspace)
         _check(lib().afps_plan_upload(self._plan, ctypes.c_void_p(self.workspace.data_ptr()),
                                       self.workspace.numel(), _stream_handle(stream)))
         self._uploaded = True
@@ -229,6 +245,7 @@ class BatchPlan:
 
     def launch(self, xyz_all, out_all=None, stream=None, graph=False):
         out_all = self._args(xyz_all, out_all, stream)
+        _used_on(stream, xyz_all, out_all, self.workspace)
         f = lib().afps_plan_graph_launch if graph else lib().afps_plan_launch
         _check(f(self._plan, ctypes.c_void_p(xyz_all.data_ptr()), ctypes.c_void_p(out_all.data_ptr()),
                  ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(stream)))
@@ -295,6 +312,7 @@ def bin_points(xyz, axis: int, bins: int, with_points: bool = True, stream=None)
     ws = torch.empty(max(need, 256), dtype=torch.uint8, device=xyz.device)
     perm = torch.empty(max(n, 1), dtype=torch.int32, device=xyz.device)
     out = torch.empty_like(xyz) if with_points else None
+    _used_on(stream, xyz, ws, perm, out)
     _check(lib().afps_bin_points(ctypes.c_void_p(xyz.data_ptr()), n, axis, bins, ctypes.c_void_p(perm.data_ptr()),
                                  ctypes.c_void_p(out.data_ptr()) if out is not None else None,
                                  ctypes.c_void_p(ws.data_ptr()), need, _stream_handle(stream)))
@@ -316,8 +334,12 @@ def ball_query(xyz, centers, radius: float, k: int, window: int | None = None, o
         out = torch.empty((c, k), dtype=torch.int32, device=xyz.device)
     if counts is None:
         counts = torch.empty(c, dtype=torch.int32, device=xyz.device)
-    if out.shape != (c, k) or out.dtype != torch.int32 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous int32 (C, k) tensor")
+    if out.shape != (c, k) or out.dtype != torch.int32 or not out.is_contiguous() or out.device != xyz.device:
+        raise ValueError("out must be a contiguous int32 (C, k) tensor on the points' device")
+    if (counts.shape != (c,) or counts.dtype != torch.int32 or not counts.is_contiguous()
+            or counts.device != xyz.device):
+        raise ValueError("counts must be a contiguous int32 (C,) tensor on the points' device")
+    _used_on(stream, xyz, centers, out, counts)
     _check(lib().afps_ball_query(ctypes.c_void_p(xyz.data_ptr()), xyz.shape[0], ctypes.c_void_p(centers.data_ptr()),
                                  c, float(radius), int(k), -1 if window is None else int(window),
                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(counts.data_ptr()),

@@ -79,3 +79,21 @@ def test_explicit_upload_is_not_repeated(fake):
     plan.launch(torch.zeros(10, 3), out_all=torch.empty(4, dtype=torch.int32), stream=side)
     assert fake.calls == [("upload", 0x5300), ("launch", 0x5300)]
     plan.close()
+
+
+def test_ball_query_rejects_mis_sized_outputs(monkeypatch):
+    """Caller-supplied outputs of the wrong shape, type or device are refused
+    before anything is launched (a short counts tensor would be written past
+    its end)."""
+    monkeypatch.setattr(binding, "_check_points", lambda xyz: None)
+    monkeypatch.setattr(binding, "lib", lambda: pytest.fail("nothing may reach the library"))
+    xyz = torch.zeros(10, 3)
+    centers = torch.zeros(4, dtype=torch.int32)
+    good_out, good_cnt = torch.empty(4, 8, dtype=torch.int32), torch.empty(4, dtype=torch.int32)
+    for out, cnt in [(torch.empty(4, 7, dtype=torch.int32), good_cnt),
+                     (torch.empty(4, 8, dtype=torch.int64), good_cnt),
+                     (good_out, torch.empty(3, dtype=torch.int32)),
+                     (good_out, torch.empty(4, dtype=torch.float32)),
+                     (good_out, torch.empty(8, dtype=torch.int32)[::2])]:
+        with pytest.raises(ValueError):
+            binding.ball_query(xyz, centers, 0.5, 8, out=out, counts=cnt)
