@@ -391,6 +391,24 @@ def test_batch_of_256_every_cloud(B, torch_dev, occupancy):
         assert (plan.pool_waves, plan.pool_groups) == (4, 2)
 
 
+@pytest.mark.parametrize("n,groups", [(4992, 2), (4993, 1), (20160, 2), (20161, 1)])
+def test_split_pool_at_the_half_boundary(B, torch_dev, n, groups):
+    """At two waves per SIMD the plan splits each CU into two workgroups when
+    its largest sector fits half of a CU's 159 pages: 4992 points of 16-byte
+    records take 79 pages (78 blocks and the padding block), 4993 take 80;
+    20160 points of distance-only records take 79 (316 blocks of 256 bytes),
+    20161 take 80.  Either way every index is exact."""
+    torch, dev = torch_dev
+    clouds = [synth.object_cloud(n, seed=n), synth.object_cloud(3000, seed=1), synth.object_cloud(700, seed=2)]
+    sizes, cs = [len(p) for p in clouds], [600, 500, 175]
+    B.set_plan_occupancy(4.0)
+    try:
+        plan = _batch_case(B, torch, dev, clouds, cs, [1, 1, 1], [64, 32, 17], [n - 1, 0, 5], graph_replays=1)
+    finally:
+        B.set_plan_occupancy(0.0)
+    assert (plan.pool_waves, plan.pool_groups) == (4 if groups == 2 else 8, groups)
+
+
 def test_pipelined_steps_on_two_streams(B, torch_dev):
     """Consecutive steps alternating over two streams, each with its own plan
     (split pool: two workgroups per CU) and output, several replays each in
