@@ -361,6 +361,22 @@ def counter_traffic(kernel):
     return k["traffic_bytes_per_launch"] if k else None
 
 
+def shader_clock_mhz():
+    """The driver's current shader-clock level (sysfs pp_dpm_sclk, the line
+    marked '*'), in MHz, for every GPU that exposes it; None where unreadable."""
+    import glob
+    out = []
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(path) as f:
+                for line in f:
+                    if "*" in line:
+                        out.append(int("".join(ch for ch in line.split(":", 1)[1] if ch.isdigit())))
+        except (OSError, ValueError, IndexError):
+            continue
+    return out or None
+
+
 def host_cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -475,6 +491,7 @@ def main():
     plan, out = plans[0], outs[0]
     log("AFPS-NPDU plan: %d items, %d launch(es), %d stream(s)" % (plan.items, plan.launches, S))
     wall, warm = time_steps(torch, plans, xyz_all, outs, args.steps, args.warmup, streams)
+    sclk = shader_clock_mhz()
     ms_per_step = wall * 1e3 / args.steps
     value = total_samples / (wall / args.steps)
     out_np = out.cpu().numpy()
@@ -496,6 +513,7 @@ def main():
                                         "what": "ms per step, timed as the steps are (%d stream(s))" % S}
     elif args.occupancy is not None:
         res["plan_occupancy"] = args.occupancy
+    res["sclk_mhz_after_timed_steps"] = sclk
     res["batch_latency"] = {"unit": "ms", "what": "one step alone (whole batch of 256 clouds, graph launches "
                                                   "one at a time on one stream), HIP events",
                             "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
