@@ -9,28 +9,29 @@
  * never links, calls or includes it, and it shares no code with the GPU path.
  *
  * The method is a heuristic (it does not reach the plain-FPS result by another
- * route), so this oracle follows the algorithm step by step in the paper's
- * order: Algorithm 1 (FPS), Sec. III-B (AFPS sectors), Sec. III-C (NPDU).  It is
- * deliberately slow and unblocked: one sector after the other, one point after
- * the other, a full sequential argmax scan every iteration.
+ * route), so this oracle takes the steps of the method in the paper's order:
+ * plain FPS as Algorithm 1 defines it, the storage sectors of Sec. III-B, the
+ * neighbourhood refresh of Sec. III-C.  It is deliberately slow and
+ * unblocked: one sector after the other, one point after the other, a full
+ * sequential scan for the farthest point after every pick.
  *
  * Readings of points the paper leaves open (each is used identically by the
  * GPU path; the numbering follows the design notes):
  *   - distance: squared Euclidean in fp32, ((dx*dx + dy*dy) + dz*dz) with
  *     dx = P[j].x - P[cur].x, every operation rounded to nearest, no fused
- *     multiply-add (Algorithm 1, geo_dist; the argmax does not change under
- *     sqrt, and skipping sqrt creates no extra rounding ties);
- *   - initial distance 1e10 (Algorithm 1 initialisation), exact in fp32;
- *   - argmax ties go to the lowest index (a sequential scan with strict '>');
+ *     multiply-add (the paper names a Euclidean distance; the farthest point
+ *     does not change under sqrt, and skipping sqrt adds no rounding ties);
+ *   - every running distance starts at 1e10, as in the paper, exact in fp32;
+ *   - ties for the farthest point go to the lowest index (a sequential scan
+ *     with strict '>');
  *   - start: sector s starts at its local point (start mod n_s);
  *   - sectors are contiguous storage ranges: the first N mod M sectors hold one
  *     extra point, the first C mod M sectors take one extra sample (Sec. III-B:
  *     C/M iterations per sector);
- *   - NPDU window: the new sample plus floor(k/2) storage neighbours below and
- *     ceil(k/2) above, truncated at the sector's edges (Sec. III-C, Fig. 3);
- *     there is no full distance pass on the first iteration;
- *   - the last sample's own distance update is never applied (Algorithm 1 ends
- *     after storing the last sample).
+ *   - NPDU neighbourhood: the new sample plus floor(k/2) storage neighbours
+ *     below and ceil(k/2) above, cut off at the sector's ends (Sec. III-C,
+ *     Fig. 3); there is no refresh of the whole sector after the first pick;
+ *   - the last pick refreshes no distance (the loop ends once it is stored).
  * The alternative readings of the three NPDU points are available as flags
  * (ORACLE_NPDU_* below), so that their effect can be measured.
  *
@@ -63,7 +64,7 @@
 #define ORACLE_NPDU_SHIFT_EDGES 2
 #define ORACLE_NPDU_K_WITH_SELF 4
 
-/* Algorithm 1: every distance starts at 1e10. */
+/* Value every running distance starts from (exact in fp32). */
 static const float INITIAL_DISTANCE = 1e10f;
 
 /*
@@ -83,7 +84,7 @@ void oracle_sector(int32_t n, int32_t c, int32_t m, int32_t s,
     *first_sample = s * qc + (s < rc ? s : rc);
 }
 
-/* Algorithm 1, geo_dist: squared Euclidean distance, fixed operation order. */
+/* Squared Euclidean distance of p from q, in a fixed operation order. */
 static float squared_distance(const float *p, const float *q)
 {
     float dx = p[0] - q[0];
@@ -97,62 +98,95 @@ static float squared_distance(const float *p, const float *q)
 }
 
 /*
- * Local FPS on one sector (Algorithm 1 applied to P[first .. first+n)),
- * optionally with NPDU (k >= 0).  Writes c global indices to out[0..c).
- * dist is the sector's Distance array (n entries).  Returns the number of
- * distance evaluations.
+ * The storage range [*lo, *hi] (sector-local) whose distances a new sample at
+ * local index cur refreshes.  The whole sector when `whole` is set (FPS and
+ * AFPS, or the full first refresh of the FIRST_FULL reading); otherwise the
+ * NPDU neighbourhood of Sec. III-C: the sample with `below` points under it
+ * and `above` over it, cut off (or, SHIFT_EDGES, pushed back inside) at the
+ * ends of the sector.
+ */
+static void refresh_range(int32_t n, int32_t k, int32_t flags, int whole, int32_t cur,
+                          int32_t *lo, int32_t *hi)
+{
+    if (whole) {
+        *lo = 0;
+        *hi = n - 1;
+        return;
+    }
+    int32_t below, above;
+    if (flags & ORACLE_NPDU_K_WITH_SELF) {
+        below = (k - 1) / 2;                           /* k >= 1 points counting the sample */
+        above = (k - 1) - below;
+    } else {
+        below = k / 2;                                 /* the sample and k neighbours */
+        above = k - k / 2;
+    }
+    int64_t from = (int64_t)cur - below, to = (int64_t)cur + above;
+    if (flags & ORACLE_NPDU_SHIFT_EDGES) {
+        if (from < 0) {                                /* slide up, off the bottom end */
+            to -= from;
+            from = 0;
+        }
+        if (to > n - 1) {                              /* slide down, off the top end */
+            from -= to - (n - 1);
+            to = n - 1;
+        }
+    }
+    *lo = from < 0 ? 0 : (int32_t)from;                /* never outside the sector */
+    *hi = to > n - 1 ? n - 1 : (int32_t)to;
+}
+
+/*
+ * Lower the running distance of every point in [lo, hi] of the sector pts to
+ * its squared distance from `sample` when that is smaller.  Returns the
+ * number of distances computed.
+ */
+static int64_t relax(const float *pts, int32_t lo, int32_t hi, const float *sample, float *dist)
+{
+    for (int32_t j = lo; j <= hi; ++j) {
+        float d = squared_distance(pts + 3 * (int64_t)j, sample);
+        dist[j] = d < dist[j] ? d : dist[j];
+    }
+    return (int64_t)hi - lo + 1;
+}
+
+/* The lowest index whose running distance is the largest of the sector. */
+static int32_t farthest(const float *dist, int32_t n)
+{
+    int32_t far = 0;
+    for (int32_t j = 1; j < n; ++j)
+        if (dist[j] > dist[far])
+            far = j;
+    return far;
+}
+
+/*
+ * Farthest point sampling on one sector, the points P[first .. first+n):
+ * c picks, the first at local index start mod n, each further one the point
+ * farthest from the picks so far as the running distances see it.  After
+ * each pick only refresh_range's points are refreshed (all of them without
+ * NPDU, k < 0); the last pick refreshes nothing, since no pick follows it.
+ * Writes the c global indices to out[0..c) and leaves the running distances
+ * in dist[0..n).  Returns the number of distances computed.
  */
 static int64_t sample_sector(const float *P, int32_t first, int32_t n, int32_t c,
                              int32_t k, int32_t flags, int32_t start, float *dist, int32_t *out)
 {
-    int64_t evaluations = 0;
+    const float *pts = P + 3 * (int64_t)first;
     for (int32_t j = 0; j < n; ++j)
-        dist[j] = INITIAL_DISTANCE;                    /* Algorithm 1: Distance = 1e10 */
-
-    int32_t cur = start % n;                           /* first sample of the sector */
-    out[0] = first + cur;
-
-    for (int32_t i = 1; i < c; ++i) {                  /* Algorithm 1: i = 1 .. n_point-1 */
-        /* Update set: the whole sector (FPS / AFPS), or the NPDU window. */
-        int32_t lo = 0, hi = n - 1;
-        if (k >= 0 && !(i == 1 && (flags & ORACLE_NPDU_FIRST_FULL))) {
-            int32_t below, above;
-            if (flags & ORACLE_NPDU_K_WITH_SELF) {
-                below = (k - 1) / 2;                   /* k >= 1: k points with the sample */
-                above = (k - 1) - below;
-            } else {
-                below = k / 2;                         /* the sample and k neighbours */
-                above = k - k / 2;
-            }
-            int64_t l = (int64_t)cur - below, h = (int64_t)cur + above;
-            if (flags & ORACLE_NPDU_SHIFT_EDGES) {
-                if (l < 0) {                           /* move right, off the lower edge */
-                    h -= l;
-                    l = 0;
-                }
-                if (h > n - 1) {                       /* move left, off the upper edge */
-                    l -= h - (n - 1);
-                    h = n - 1;
-                }
-            }
-            lo = l < 0 ? 0 : (int32_t)l;               /* truncate to the sector */
-            hi = h > n - 1 ? n - 1 : (int32_t)h;
-        }
-        const float *sample = P + 3 * (int64_t)(first + cur);
-        for (int32_t j = lo; j <= hi; ++j) {           /* Algorithm 1: distance update */
-            float d = squared_distance(P + 3 * (int64_t)(first + j), sample);
-            ++evaluations;
-            if (d <= dist[j])
-                dist[j] = d;
-        }
-        int32_t best = 0;                              /* Algorithm 1: argmax(Distance) */
-        for (int32_t j = 1; j < n; ++j)
-            if (dist[j] > dist[best])
-                best = j;
-        cur = best;
-        out[i] = first + cur;                          /* Algorithm 1: Sampled[i] */
+        dist[j] = INITIAL_DISTANCE;
+    int64_t computed = 0;
+    int32_t pick = start % n;
+    out[0] = first + pick;
+    for (int32_t t = 1; t < c; ++t) {
+        const int whole = k < 0 || (t == 1 && (flags & ORACLE_NPDU_FIRST_FULL));
+        int32_t lo, hi;
+        refresh_range(n, k, flags, whole, pick, &lo, &hi);
+        computed += relax(pts, lo, hi, pts + 3 * (int64_t)pick, dist);
+        pick = farthest(dist, n);
+        out[t] = first + pick;
     }
-    return evaluations;
+    return computed;
 }
 
 /*
@@ -208,7 +242,7 @@ int oracle_afps(const float *P, int32_t n, int32_t c, int32_t m, int32_t k,
     return oracle_afps_ex(P, n, c, m, k, 0, start, out, dist, evals);
 }
 
-/* Plain FPS (Algorithm 1): AFPS with one sector and no NPDU. */
+/* Plain FPS: AFPS with one sector and no NPDU. */
 int oracle_fps(const float *P, int32_t n, int32_t c, int32_t start, int32_t *out,
                float *dist, int64_t *evals)
 {

@@ -10,8 +10,10 @@ approximate order of the paper's footnote to Table II, where every point of a
 later bin has a larger coordinate than every point of an earlier bin and
 points inside a bin are in no particular order.
 
-bin_points(points, axis, bins) computes, in fp32 (the decision of a point's
-bin is taken in the arithmetic of the GPU kernel):
+bin_points(points, axis, bins) computes, in fp32 (the paper fixes no
+precision; the coordinates are fp32, and a float that decides an integer bin
+must be taken in one stated arithmetic, so this reading of Sec. III-A fixes
+fp32 with one correctly rounded division and no fused multiply-add):
     lo, hi = smallest and largest coordinate along `axis`
     scale  = bins / (hi - lo)                    (one correctly rounded division;
                                                   0 when hi == lo)

@@ -19,26 +19,26 @@ MUTANTS = {
     "drop_dz": ("return xy + zz;", "return xy;"),
     "wrong_sign": ("float dy = p[1] - q[1];", "float dy = p[1] + q[1];"),
     "wrong_coordinate": ("float dz = p[2] - q[2];", "float dz = p[2] - q[1];"),
-    "transposed_operand": ("float d = squared_distance(P + 3 * (int64_t)(first + j), sample);",
-                           "float d = squared_distance(P + 3 * (int64_t)(first + j), P + 3 * (int64_t)(first + j - (j > 0)));"),
-    "tie_to_highest": ("if (dist[j] > dist[best])", "if (dist[j] >= dist[best])"),
-    "update_reversed": ("if (d <= dist[j])", "if (d >= dist[j])"),
+    "transposed_operand": ("float d = squared_distance(pts + 3 * (int64_t)j, sample);",
+                           "float d = squared_distance(pts + 3 * (int64_t)j, pts + 3 * (int64_t)(j - (j > 0)));"),
+    "tie_to_highest": ("if (dist[j] > dist[far])", "if (dist[j] >= dist[far])"),
+    "update_reversed": ("dist[j] = d < dist[j] ? d : dist[j];", "dist[j] = d > dist[j] ? d : dist[j];"),
     "sample_split_floor": ("*first_sample = s * qc + (s < rc ? s : rc);",
                            "*first_sample = s * qc + (s < rc ? 0 : rc);"),
     "point_split_last": ("*num_points = qn + (s < rn ? 1 : 0);",
                          "*num_points = qn + (s >= m - rn ? 1 : 0);"),
-    "window_floor_ceil_swapped": ("below = k / 2;                         /* the sample and k neighbours */\n                above = k - k / 2;",
-                                  "below = k - k / 2;\n                above = k / 2;"),
-    "window_excludes_top": ("hi = h > n - 1 ? n - 1 : (int32_t)h;", "hi = h > n - 1 ? n - 1 : (int32_t)h - 1;"),
-    "start_not_local": ("int32_t cur = start % n;", "int32_t cur = 0;"),
+    "window_floor_ceil_swapped": ("below = k / 2;                                 /* the sample and k neighbours */\n        above = k - k / 2;",
+                                  "below = k - k / 2;\n        above = k / 2;"),
+    "window_excludes_top": ("*hi = to > n - 1 ? n - 1 : (int32_t)to;", "*hi = to > n - 1 ? n - 1 : (int32_t)to - 1;"),
+    "start_not_local": ("int32_t pick = start % n;", "int32_t pick = 0;"),
     "initial_1e9": ("INITIAL_DISTANCE = 1e10f;", "INITIAL_DISTANCE = 1e9f;"),
-    "local_output_index": ("out[i] = first + cur;", "out[i] = cur;"),
-    "npdu_full_first_pass": ("if (k >= 0 && !(i == 1 && (flags & ORACLE_NPDU_FIRST_FULL))) {",
-                             "if (k >= 0 && i > 1) {"),
-    "first_full_every_iteration": ("!(i == 1 && (flags & ORACLE_NPDU_FIRST_FULL))",
-                                   "!(flags & ORACLE_NPDU_FIRST_FULL)"),
-    "shift_wrong_way": ("                    h -= l;", "                    h += l;"),
-    "shift_never_left": ("                    l -= h - (n - 1);", "                    l -= 0;"),
+    "local_output_index": ("out[t] = first + pick;", "out[t] = pick;"),
+    "npdu_full_first_pass": ("const int whole = k < 0 || (t == 1 && (flags & ORACLE_NPDU_FIRST_FULL));",
+                             "const int whole = k < 0 || t == 1;"),
+    "first_full_every_iteration": ("(t == 1 && (flags & ORACLE_NPDU_FIRST_FULL))",
+                                   "(flags & ORACLE_NPDU_FIRST_FULL)"),
+    "shift_wrong_way": ("            to -= from;", "            to += from;"),
+    "shift_never_left": ("            from -= to - (n - 1);", "            from -= 0;"),
     "self_window_not_reduced": ("below = (k - 1) / 2;", "below = k / 2;"),
 }
 
