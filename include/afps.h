@@ -179,6 +179,28 @@ int afps_plan_launch(const afps_plan *plan, const float *xyz_all, int32_t *out_a
 int afps_plan_graph_launch(afps_plan *plan, const float *xyz_all, int32_t *out_all,
                            void *workspace, void *stream);
 
+/*
+ * afps_plan_launch for callers that cannot allocate device memory and cannot
+ * bring a workspace (tight serving loops, harnesses that forbid hipMalloc):
+ * the plan's workspace is a static array of 1 MiB in device memory that the
+ * library holds on each GPU it runs on until the process ends, so the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * It copies the plan's tables into that array on `stream` and launches the
+ * same kernels as afps_plan_launch, whose reset kernel clears the queue
+ * counters first.  Every call on a GPU shares that GPU's array, which keeps
+ * the last call's contents: calls that overlap on one GPU (several streams
+ * or threads, or with a plan launched this way still running) race on it and
+ * must be serialised by the caller.  The plan must have been created with the
+ * current device current (AFPS_ERR_ARG otherwise).  AFPS_ERR_WORKSPACE, with
+ * nothing copied or launched, for a plan of more than afps_noalloc_max_items()
+ * sectors.  Not for stream capture (the tables are copied from pageable host
+ * memory).
+ */
+int afps_plan_launch_noalloc(const afps_plan *plan, const float *xyz_all, int32_t *out_all,
+                             void *stream);
+/* Sectors (work items) a plan may have for afps_plan_launch_noalloc. */
+int32_t afps_noalloc_max_items(void);
+
 /* Number of work items (sectors) and persistent launches of the plan. */
 int32_t afps_plan_items(const afps_plan *plan);
 int32_t afps_plan_launches(const afps_plan *plan);

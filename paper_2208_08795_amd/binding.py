@@ -63,6 +63,8 @@ def lib():
             "afps_plan_upload": ([vp, vp, sz, vp], ctypes.c_int),
             "afps_plan_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
             "afps_plan_graph_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
+            "afps_plan_launch_noalloc": ([vp, vp, vp, vp], ctypes.c_int),
+            "afps_noalloc_max_items": ([], i32),
             "afps_plan_items": ([vp], i32),
             "afps_plan_launches": ([vp], i32),
             "afps_plan_pool_waves": ([vp], i32),
@@ -249,6 +251,19 @@ class BatchPlan:
         f = lib().afps_plan_graph_launch if graph else lib().afps_plan_launch
         _check(f(self._plan, ctypes.c_void_p(xyz_all.data_ptr()), ctypes.c_void_p(out_all.data_ptr()),
                  ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(stream)))
+        return out_all
+
+    def launch_noalloc(self, xyz_all, out_all=None, stream=None):
+        """Launch with the library's static per-GPU workspace instead of the
+        plan's own (afps_plan_launch_noalloc): no device allocation by the
+        library; calls that overlap on one GPU race on that workspace."""
+        _check_points(xyz_all)
+        if xyz_all.shape[0] < self.total_points:
+            raise ValueError("xyz_all holds fewer points than the plan's clouds")
+        out_all = _out(xyz_all, self.total_samples, out_all)
+        _used_on(stream, xyz_all, out_all)
+        _check(lib().afps_plan_launch_noalloc(self._plan, ctypes.c_void_p(xyz_all.data_ptr()),
+                                              ctypes.c_void_p(out_all.data_ptr()), _stream_handle(stream)))
         return out_all
 
     def split(self, out_all):

@@ -148,6 +148,14 @@ int npdu_lds_bytes(const NpduEntry& v, int n) { return 4 * npdu_lds_words(n, v.x
 
 // ------------------------------------------------------------ devices
 
+// Workspace of afps_plan_launch_noalloc, for callers that cannot allocate
+// device memory: static device memory, one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it names a stand-in, not device memory): it uses the address that
+// hipGetSymbolAddress returns on each device (DeviceState::scratch).
+constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct DeviceState {
     bool ready = false;
     int cu_count = 0;
@@ -159,6 +167,7 @@ struct DeviceState {
     std::mutex check_mu;                     // one validation at a time per device
     std::vector<hipEvent_t> grid_events;     // last user of each block
     int grid_next = 0;
+    void* scratch = nullptr;                 // this device's copy of `scratch`
 };
 
 constexpr int kHelperStreams = 4;
@@ -173,6 +182,12 @@ int device_state(DeviceState** out) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
     DeviceState& d = g_devices[dev];
     if (!d.ready) {
+        // The device address of this GPU's static scratch (with this device
+        // current, as hipGetDevice reported it above).
+        void* sp = nullptr;
+        AFPS_HIP(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+        if (!sp) return fail(AFPS_ERR_HIP, "hipGetSymbolAddress(scratch) returned no address");
+        d.scratch = sp;
         int cus = 0, lds = 0;
         AFPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         AFPS_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -984,25 +999,35 @@ int32_t afps_plan_pool_groups_per_cu(const afps_plan* plan) { return plan ? plan
 
 void afps_plan_destroy(afps_plan* plan) { delete plan; }
 
+}  // extern "C"
+
+namespace {
+
+// Copy the plan's tables (pool queues, seeds, work items) into a workspace.
+// Pageable sources: the copies have consumed the host tables when this returns.
+int upload_tables(const afps_plan* plan, void* workspace, hipStream_t stream) {
+    if (!plan->queues.empty())
+        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolTableOffset, plan->queues.data(),
+                                plan->queues.size() * sizeof(PoolQueue), hipMemcpyHostToDevice, stream));
+    if (!plan->seeds.empty())
+        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolSeedOffset, plan->seeds.data(),
+                                plan->seeds.size() * sizeof(PoolSeed), hipMemcpyHostToDevice, stream));
+    AFPS_HIP(hipMemcpyAsync((char*)workspace + kItemsOffset, plan->items.data(),
+                            plan->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, stream));
+    return AFPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int afps_plan_upload(afps_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
     if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
     if (plan->items.empty()) return AFPS_OK;
     if (!workspace || workspace_bytes < plan->ws_bytes)
         return fail(AFPS_ERR_WORKSPACE, "workspace needs " + std::to_string(plan->ws_bytes) + " bytes");
     if (((uintptr_t)workspace & 255) != 0) return fail(AFPS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    // Pageable sources: the copies have consumed the host tables when this returns.
-    if (!plan->queues.empty())
-        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolTableOffset, plan->queues.data(),
-                                plan->queues.size() * sizeof(PoolQueue), hipMemcpyHostToDevice,
-                                (hipStream_t)stream));
-    if (!plan->seeds.empty())
-        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolSeedOffset, plan->seeds.data(),
-                                plan->seeds.size() * sizeof(PoolSeed), hipMemcpyHostToDevice,
-                                (hipStream_t)stream));
-    AFPS_HIP(hipMemcpyAsync((char*)workspace + kItemsOffset, plan->items.data(),
-                            plan->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
-                            (hipStream_t)stream));
-    return AFPS_OK;
+    return upload_tables(plan, workspace, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -1122,6 +1147,35 @@ int afps_plan_graph_launch(afps_plan* plan, const float* xyz_all, int32_t* out_a
     }
     AFPS_HIP(hipGraphLaunch(plan->exec, stream));
     return AFPS_OK;
+}
+
+int afps_plan_launch_noalloc(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* stream_) {
+    if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
+    if (plan->items.empty()) return AFPS_OK;
+    if (!xyz_all || !out_all) return fail(AFPS_ERR_NULL, "xyz_all and out_all must be non-null");
+    if (plan->ws_bytes > kScratchBytes)
+        return fail(AFPS_ERR_WORKSPACE, "the plan needs " + std::to_string(plan->ws_bytes) +
+                                            " bytes of workspace; the static scratch holds " +
+                                            std::to_string(kScratchBytes) + " (at most " +
+                                            std::to_string(afps_noalloc_max_items()) + " sectors)");
+    DeviceState* d;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    int dev = 0;
+    AFPS_HIP(hipGetDevice(&dev));
+    if (dev != plan->device)
+        return fail(AFPS_ERR_ARG, "the plan was built on device " + std::to_string(plan->device) +
+                                      ", the current device is " + std::to_string(dev));
+    hipStream_t stream = (hipStream_t)stream_;
+    if (g_checking && (rc = check_plan_clouds(plan, xyz_all, stream))) return rc;
+    // The tables go into this device's scratch on the launch stream, then the
+    // same launches as afps_plan_launch; the reset kernel clears the counters.
+    if ((rc = upload_tables(plan, d->scratch, stream))) return rc;
+    return plan_launch_impl(plan, xyz_all, out_all, d->scratch, stream);
+}
+
+int32_t afps_noalloc_max_items(void) {
+    return (int32_t)((kScratchBytes - kItemsOffset) / sizeof(WorkItem));
 }
 
 size_t afps_batched_workspace_bytes(const afps_cloud_desc* descs, int32_t batch) {
