@@ -19,9 +19,16 @@
  *   stream   a hipStream_t passed as void* (NULL = the default stream).  Every
  *            call is asynchronous on that stream; results are valid once the
  *            caller has synchronised it.
- *   Ownership: the caller allocates and frees every buffer.  The single-cloud
- *   calls allocate nothing; batch plans allocate host memory only (the device
- *   side lives in the caller's workspace).
+ *   Ownership: the caller allocates and frees every buffer.  No sampling call
+ *   allocates device memory: the library's own device state (barrier blocks
+ *   of the multi-workgroup FPS, a failure word, events ordering their reuse)
+ *   is static device memory or is made once per device, by afps_init or by
+ *   the first call on that device.  Batch plans allocate host memory only
+ *   (the device side lives in the caller's workspace).
+ *   Device-side failures: the only waits inside kernels are bounded (see
+ *   afps_set_spin_limit); a kernel that gives one up leaves -1 in the outputs
+ *   it could not finish and records the failure, which afps_device_status
+ *   (any call) and afps_plan_status (batch plans) report as AFPS_ERR_DEVICE.
  *   Arithmetic: squared Euclidean distance in fp32, ((dx*dx + dy*dy) + dz*dz),
  *   no fused multiply-add; initial distance 1e10; argmax ties go to the lowest
  *   index.  Results are bit-identical to a sequential evaluation of the paper's
@@ -105,6 +112,23 @@ int afps_afps_npdu(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
 int afps_afps_npdu_ex(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t k,
                       int32_t start, int32_t flags, int32_t *out_idx, void *stream);
 
+/*
+ * Set up the library's state on the current device (kernel attributes, the
+ * static barrier blocks and failure word, events): every call does this on
+ * its first use of a device; calling it first keeps that work out of a later
+ * call (for instance one inside a stream capture).  AFPS_ERR_HIP on failure.
+ */
+int afps_init(void);
+
+/*
+ * Device-side failures on the current device: waits for `stream`, then
+ * returns AFPS_ERR_DEVICE if any kernel of the library on this device has
+ * given up a bounded wait since the record was last cleared (its unfinished
+ * outputs hold -1), else AFPS_OK; clear != 0 clears the record (ordered on
+ * `stream`).  The record is shared by every stream and thread on the device.
+ */
+int afps_device_status(void *stream, int32_t clear);
+
 /* Largest sector (points) a single workgroup holds in registers. */
 int32_t afps_max_sector_points(void);
 
@@ -178,6 +202,36 @@ int afps_plan_launch(const afps_plan *plan, const float *xyz_all, int32_t *out_a
  */
 int afps_plan_graph_launch(afps_plan *plan, const float *xyz_all, int32_t *out_all,
                            void *workspace, void *stream);
+
+/*
+ * Status of the plan's last launch with `workspace`: waits for `stream`, then
+ * returns AFPS_ERR_DEVICE if a wave of that launch gave up a bounded wait
+ * (the sectors it could not run hold -1 in full), else AFPS_OK.  Each launch
+ * clears the word first.
+ */
+int afps_plan_status(const afps_plan *plan, const void *workspace, void *stream);
+
+/*
+ * afps_plan_launch that also records, for every NPDU sector of the plan, 64
+ * bytes of timestamps into `stamps` (DEVICE, >= afps_plan_items(plan) * 64
+ * bytes, 64-byte aligned; entry i belongs to the plan's work item i):
+ *   uint64 take, loaded, end  shader-clock counter (cycles) when a wave took
+ *                             the sector, when its points were in LDS, and
+ *                             when its last pick was written
+ *   uint64 take_rt, end_rt    constant-rate counter at take and end
+ *   int32  item, n, c, k      the work item and its sector's points, samples
+ *                             and window
+ *   uint32 hw_id, xcc_id      hardware id of the wave (CU, SIMD, slot) and
+ *                             its XCC
+ * so that (end - loaded) / (c - 1) is the sector's cycles per iteration.
+ * Entries of full-update (FPS / AFPS) sectors are not written.
+ */
+int afps_plan_launch_stamped(const afps_plan *plan, const float *xyz_all, int32_t *out_all,
+                             void *workspace, void *stamps, size_t stamp_bytes, void *stream);
+
+/* Rate of the constant-rate counter of the stamps (kHz) on the current
+ * device; 0 if the runtime does not report it. */
+int32_t afps_wall_clock_khz(void);
 
 /*
  * afps_plan_launch for callers that cannot allocate device memory and cannot
@@ -269,9 +323,12 @@ int afps_afps_variant(const float *xyz, int32_t n, int32_t c, int32_t m, int32_t
 int afps_set_plan_occupancy(float waves_per_simd);
 
 /*
- * Bound on the polls of one grid-barrier wait in the multi-workgroup plain-FPS
- * kernel (default 4M).  A wait that exceeds it marks the launch failed: every
- * workgroup returns and the unfinished outputs hold -1.  Process-wide.
+ * Bound on the polls of one wait inside a kernel (default 4M): a grid barrier
+ * of the multi-workgroup plain-FPS kernel, or the page-allocation lock and
+ * free pages of the pooled NPDU kernel.  A wait that exceeds it fails the
+ * launch: the grid kernel's workgroups all return with -1 in the unfinished
+ * outputs; a pooled wave marks every sector still queued -1.  Either records
+ * AFPS_ERR_DEVICE (afps_device_status, afps_plan_status).  Process-wide.
  */
 int afps_set_spin_limit(uint32_t polls);
 

@@ -64,6 +64,11 @@ def lib():
             "afps_plan_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
             "afps_plan_graph_launch": ([vp, vp, vp, vp, vp], ctypes.c_int),
             "afps_plan_launch_noalloc": ([vp, vp, vp, vp], ctypes.c_int),
+            "afps_plan_launch_stamped": ([vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+            "afps_plan_status": ([vp, vp, vp], ctypes.c_int),
+            "afps_device_status": ([vp, i32], ctypes.c_int),
+            "afps_init": ([], ctypes.c_int),
+            "afps_wall_clock_khz": ([], i32),
             "afps_noalloc_max_items": ([], i32),
             "afps_plan_items": ([vp], i32),
             "afps_plan_launches": ([vp], i32),
@@ -253,6 +258,29 @@ class BatchPlan:
                  ctypes.c_void_p(self.workspace.data_ptr()), _stream_handle(stream)))
         return out_all
 
+    def launch_stamped(self, xyz_all, out_all=None, stream=None):
+        """Eager launch that also records each NPDU sector's timestamps
+        (afps_plan_launch_stamped); returns (out_all, stamps) with stamps an
+        int64 (items, 8) tensor: take, loaded, end (shader clock), take_rt,
+        end_rt (constant-rate clock), then (item, n) (c, k) (hw_id, xcc_id) as
+        pairs of int32 packed in the last three columns."""
+        torch = _torch()
+        out_all = self._args(xyz_all, out_all, stream)
+        stamps = torch.zeros((max(self.items, 1), 8), dtype=torch.int64, device=xyz_all.device)
+        _used_on(stream, xyz_all, out_all, self.workspace, stamps)
+        _check(lib().afps_plan_launch_stamped(self._plan, ctypes.c_void_p(xyz_all.data_ptr()),
+                                              ctypes.c_void_p(out_all.data_ptr()),
+                                              ctypes.c_void_p(self.workspace.data_ptr()),
+                                              ctypes.c_void_p(stamps.data_ptr()), stamps.numel() * 8,
+                                              _stream_handle(stream)))
+        return out_all, stamps
+
+    def status(self, stream=None):
+        """Raise AfpsError (AFPS_ERR_DEVICE) if a wave of the last launch gave
+        up a bounded wait; waits for the stream."""
+        _check(lib().afps_plan_status(self._plan, ctypes.c_void_p(self.workspace.data_ptr()),
+                                      _stream_handle(stream)))
+
     def launch_noalloc(self, xyz_all, out_all=None, stream=None):
         """Launch with the library's static per-GPU workspace instead of the
         plan's own (afps_plan_launch_noalloc): no device allocation by the
@@ -284,16 +312,63 @@ class BatchPlan:
 
 
 def batched(clouds, cs, ms, ks, starts=None, graph=False, stream=None):
-    """Sample a list of (N_i, 3) device tensors in one batch; returns per-cloud indices."""
+    """Sample a list of (N_i, 3) device tensors in one batch plan; returns
+    per-cloud indices, ready on the current stream.  With `stream`, the launch
+    runs there after the current stream's pending work (the packed input is
+    written on the current stream)."""
     torch = _torch()
     starts = starts or [0] * len(clouds)
     plan = BatchPlan([c.shape[0] for c in clouds], cs, ms, ks, starts, device=clouds[0].device)
     xyz_all = torch.cat(list(clouds), dim=0).contiguous()
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
     out = plan.launch(xyz_all, stream=stream, graph=graph)
+    if stream is not None:
+        torch.cuda.current_stream().wait_stream(stream)
     res = [o.clone() for o in plan.split(out)]
-    torch.cuda.current_stream().synchronize()
+    # the plan's graph and events may still be in use on the launch stream
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
     plan.close()
     return res
+
+
+def batched_oneshot(xyz_all, sizes, cs, ms, ks, starts, out_all=None, stream=None, flags=None):
+    """afps_batched: plan, upload and launch in one call on host descriptors
+    for clouds packed back to back in xyz_all; returns the packed indices."""
+    torch = _torch()
+    _check_points(xyz_all)
+    descs, total_points, total_samples = descriptors(sizes, cs, ms, ks, starts, flags)
+    if xyz_all.shape[0] < total_points:
+        raise ValueError("xyz_all holds fewer points than the clouds")
+    out_all = _out(xyz_all, total_samples, out_all)
+    need = int(lib().afps_batched_workspace_bytes(ctypes.cast(descs, ctypes.c_void_p), len(sizes)))
+    if need == 0 and len(sizes) > 0:
+        raise AfpsError(-2, lib().afps_last_error().decode())
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=xyz_all.device)
+    _used_on(stream, xyz_all, out_all, ws)
+    _check(lib().afps_batched(ctypes.c_void_p(xyz_all.data_ptr()), ctypes.cast(descs, ctypes.c_void_p), len(sizes),
+                              ctypes.c_void_p(out_all.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              _stream_handle(stream)))
+    return out_all
+
+
+def device_status(stream=None):
+    """Raise AfpsError (AFPS_ERR_DEVICE) if a kernel on the current device has
+    given up a bounded wait since the record was last cleared."""
+    _check(lib().afps_device_status(_stream_handle(stream), 0))
+
+
+def clear_device_status(stream=None) -> bool:
+    """Clear the device's failure record; True if a failure was recorded."""
+    rc = lib().afps_device_status(_stream_handle(stream), 1)
+    if rc not in (0, -7):
+        _check(rc)
+    return rc == -7
+
+
+def init():
+    """Set up the library's state on the current device."""
+    _check(lib().afps_init())
 
 
 def workspace_bytes_for_items(items: int) -> int:

@@ -156,22 +156,30 @@ int npdu_lds_bytes(const NpduEntry& v, int n) { return 4 * npdu_lds_words(n, v.x
 constexpr size_t kScratchBytes = size_t(1) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
+constexpr int kHelperStreams = 4;
+constexpr int kGridBlocks = 16;
+
+// The barrier blocks of the multi-workgroup plain-FPS kernel and the
+// device's failure word (device_words[0]: set by any kernel whose bounded
+// wait gave up; afps_device_status reads it), in static device memory held
+// until the process ends, so that no sampling call allocates.
+static __device__ __align__(256) unsigned char grid_blocks[kGridBlocks * kGridSyncBytes];
+static __device__ __align__(256) unsigned device_words[64];
+
 struct DeviceState {
     bool ready = false;
     int cu_count = 0;
     size_t max_lds = 0;
     int pool_pages = 0;                      // LDS pages of one pooled-NPDU workgroup
     std::vector<hipStream_t> helpers;        // bucket streams for batch plans
-    void* grid_pool = nullptr;               // grid-barrier blocks
+    void* grid_pool = nullptr;               // this device's copy of grid_blocks
+    unsigned* status = nullptr;              // this device's failure word (device_words[0])
     CheckResult* check_buf = nullptr;        // validation results (kCheckClouds), on first use
     std::mutex check_mu;                     // one validation at a time per device
     std::vector<hipEvent_t> grid_events;     // last user of each block
     int grid_next = 0;
     void* scratch = nullptr;                 // this device's copy of `scratch`
 };
-
-constexpr int kHelperStreams = 4;
-constexpr int kGridBlocks = 16;
 
 std::mutex g_dev_mu;
 std::map<int, DeviceState> g_devices;
@@ -188,6 +196,20 @@ int device_state(DeviceState** out) {
         AFPS_HIP(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
         if (!sp) return fail(AFPS_ERR_HIP, "hipGetSymbolAddress(scratch) returned no address");
         d.scratch = sp;
+        void* gp = nullptr;
+        void* wp = nullptr;
+        AFPS_HIP(hipGetSymbolAddress(&gp, HIP_SYMBOL(grid_blocks)));
+        AFPS_HIP(hipGetSymbolAddress(&wp, HIP_SYMBOL(device_words)));
+        if (!gp || !wp) return fail(AFPS_ERR_HIP, "hipGetSymbolAddress returned no address");
+        d.grid_pool = gp;
+        d.status = (unsigned*)wp;
+        // Events that order the reuse of each barrier block, created here so
+        // that no sampling call creates a runtime object.
+        while ((int)d.grid_events.size() < kGridBlocks) {
+            hipEvent_t e;
+            AFPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            d.grid_events.push_back(e);
+        }
         int cus = 0, lds = 0;
         AFPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         AFPS_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -376,14 +398,6 @@ int launch_grid_fps(const float* xyz, int32_t n, int32_t c, int32_t start, int32
     hipEvent_t ev;
     {
         std::lock_guard<std::mutex> lk(g_dev_mu);
-        if (!d->grid_pool) {
-            AFPS_HIP(hipMalloc(&d->grid_pool, (size_t)kGridBlocks * kGridSyncBytes));
-            for (int i = 0; i < kGridBlocks; ++i) {
-                hipEvent_t e;
-                AFPS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-                d->grid_events.push_back(e);
-            }
-        }
         const int slot = d->grid_next;
         d->grid_next = (slot + 1) % kGridBlocks;
         block = (char*)d->grid_pool + (size_t)slot * kGridSyncBytes;
@@ -393,8 +407,9 @@ int launch_grid_fps(const float* xyz, int32_t n, int32_t c, int32_t start, int32
         void* rargs[] = {&block};
         AFPS_HIP(hipLaunchKernel(grid_reset_kernel(), dim3(1), dim3(64), rargs, 0, stream));
         unsigned spin = g_spin_limit;
+        unsigned* status = d->status;
         void* args[] = {(void*)&xyz, (void*)&n, (void*)&c, (void*)&start, (void*)&chunk,
-                        (void*)&out, &block, &spin};
+                        (void*)&out, &block, &spin, &status};
         AFPS_HIP(hipLaunchCooperativeKernel(gv->kernel, dim3(groups), dim3(64 * gv->waves), args, 0,
                                             stream));
         AFPS_HIP(hipEventRecord(ev, stream));
@@ -663,8 +678,9 @@ struct Bucket {
 
 // Workspace of a plan: [bucket counters | pool queue counters | pool queue
 // table | pool seeds | work items].
-constexpr size_t kCounterBytes = 256;                                   // one per bucket
-constexpr int kMaxBuckets = (int)(kCounterBytes / sizeof(unsigned));
+constexpr size_t kCounterBytes = 256;                                   // one per bucket, then the status word
+constexpr int kStatusWord = (int)(kCounterBytes / sizeof(unsigned)) - 1; // set by a launch whose wait gave up
+constexpr int kMaxBuckets = kStatusWord;
 constexpr size_t kPoolCounterOffset = kCounterBytes;                    // one per pool queue
 constexpr size_t kPoolTableOffset = kPoolCounterOffset + kMaxPoolQueues * sizeof(unsigned);
 constexpr size_t kPoolSeedOffset = kPoolTableOffset + kMaxPoolQueues * sizeof(PoolQueue);
@@ -1041,8 +1057,12 @@ int check_plan_clouds(const afps_plan* plan, const float* xyz_all, hipStream_t s
 }
 
 // afps_plan_launch after argument checks: launches only (capturable).
+// `stamps`: per-item timestamps of the pooled NPDU launch, or nullptr.
 int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
-                     hipStream_t stream) {
+                     hipStream_t stream, SectorStamp* stamps = nullptr) {
+    DeviceState* d;
+    int rc = device_state(&d);
+    if (rc) return rc;
     unsigned* counters = (unsigned*)workspace;
     unsigned* qtaken = (unsigned*)((char*)workspace + kPoolCounterOffset);
     const PoolQueue* queues = (const PoolQueue*)((char*)workspace + kPoolTableOffset);
@@ -1056,12 +1076,21 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
     auto launch_bucket = [&](int b, hipStream_t s) -> int {
         const Bucket& bk = plan->buckets[b];
         if (bk.pool) {
-            int nq = (int)plan->queues.size();
-            int pages = plan->pool_pages;
-            int seed_groups = (int)plan->seeds.size() / (bk.block / 64);
-            unsigned spin = g_spin_limit;
-            void* args[] = {(void*)&xyz_all, (void*)&out_all, (void*)&items, (void*)&queues,
-                            &nq, (void*)&qtaken, (void*)&seeds, &seed_groups, &pages, &spin};
+            PoolArgs pa{};
+            pa.xyz_all = xyz_all;
+            pa.out_all = out_all;
+            pa.items = items;
+            pa.queues = queues;
+            pa.qtaken = qtaken;
+            pa.seeds = seeds;
+            pa.status = counters + kStatusWord;
+            pa.dev_status = d->status;
+            pa.stamps = stamps;
+            pa.nq = (int)plan->queues.size();
+            pa.seed_groups = (int)plan->seeds.size() / (bk.block / 64);
+            pa.pool_pages = plan->pool_pages;
+            pa.spin_limit = g_spin_limit;
+            void* args[] = {&pa};
             AFPS_HIP(hipLaunchKernel(bk.kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
             return AFPS_OK;
         }
@@ -1076,9 +1105,6 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
 
     // Several variants: run them concurrently on helper streams (fork / join
     // through events, which a stream capture records as graph edges).
-    DeviceState* d;
-    int rc = device_state(&d);
-    if (rc) return rc;
     if ((rc = helper_streams(d))) return rc;
     AFPS_HIP(hipEventRecord(plan->events[0], stream));
     const int used = std::min(nb, kHelperStreams);
@@ -1176,6 +1202,58 @@ int afps_plan_launch_noalloc(const afps_plan* plan, const float* xyz_all, int32_
 
 int32_t afps_noalloc_max_items(void) {
     return (int32_t)((kScratchBytes - kItemsOffset) / sizeof(WorkItem));
+}
+
+int afps_plan_launch_stamped(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
+                             void* stamps, size_t stamp_bytes, void* stream) {
+    int rc = plan_launch_args(plan, xyz_all, out_all, workspace);
+    if (rc || plan->items.empty()) return rc;
+    if (!stamps) return fail(AFPS_ERR_NULL, "stamps must be non-null");
+    const size_t need = plan->items.size() * sizeof(SectorStamp);
+    if (stamp_bytes < need) return fail(AFPS_ERR_WORKSPACE, "stamps need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)stamps & 63) != 0) return fail(AFPS_ERR_WORKSPACE, "stamps must be 64-byte aligned");
+    if (g_checking && (rc = check_plan_clouds(plan, xyz_all, (hipStream_t)stream))) return rc;
+    return plan_launch_impl(plan, xyz_all, out_all, workspace, (hipStream_t)stream, (SectorStamp*)stamps);
+}
+
+int afps_plan_status(const afps_plan* plan, const void* workspace, void* stream_) {
+    if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
+    if (plan->items.empty()) return AFPS_OK;
+    if (!workspace) return fail(AFPS_ERR_WORKSPACE, "workspace must be non-null");
+    hipStream_t stream = (hipStream_t)stream_;
+    unsigned word = 0;
+    AFPS_HIP(hipMemcpyAsync(&word, (const unsigned*)workspace + kStatusWord, sizeof(word), hipMemcpyDeviceToHost,
+                            stream));
+    AFPS_HIP(hipStreamSynchronize(stream));
+    if (word) return fail(AFPS_ERR_DEVICE, "a wave of the plan's last launch gave up a bounded wait; "
+                                           "the sectors it could not run hold -1");
+    return AFPS_OK;
+}
+
+int afps_device_status(void* stream_, int32_t clear) {
+    DeviceState* d;
+    int rc = device_state(&d);
+    if (rc) return rc;
+    hipStream_t stream = (hipStream_t)stream_;
+    unsigned word = 0;
+    AFPS_HIP(hipMemcpyAsync(&word, d->status, sizeof(word), hipMemcpyDeviceToHost, stream));
+    if (clear) AFPS_HIP(hipMemsetAsync(d->status, 0, sizeof(unsigned), stream));
+    AFPS_HIP(hipStreamSynchronize(stream));
+    if (word) return fail(AFPS_ERR_DEVICE, "a kernel gave up a bounded wait on this device; "
+                                           "its unfinished outputs hold -1");
+    return AFPS_OK;
+}
+
+int32_t afps_wall_clock_khz(void) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return khz;
+}
+
+int afps_init(void) {
+    DeviceState* d;
+    return device_state(&d);
 }
 
 size_t afps_batched_workspace_bytes(const afps_cloud_desc* descs, int32_t batch) {

@@ -20,10 +20,14 @@
 // parity-p slot after every workgroup published the next iteration, i.e.
 // after every workgroup read the parity-p slots.
 //
-// Every wait is bounded: after `spin_limit` polls a workgroup marks the
-// launch failed and returns, and the others notice the mark and return too;
-// workgroup 0 then fills the unfinished outputs with -1.  This per-iteration
-// synchronisation is the cost the paper's sectors avoid (Sec. III-B).
+// Every wait is bounded: after `spin_limit` polls a wave marks the launch
+// failed (and the device's failure word, which afps_device_status reports)
+// and returns; the other workgroups notice the mark and return too, and the
+// waves of its own workgroup return together with it (a flag in LDS, read
+// after the next candidate exchange, so that no wave goes on with a
+// candidate its sibling never wrote).  Workgroup 0 fills the unfinished
+// outputs with -1.  This per-iteration synchronisation is the cost the
+// paper's sectors avoid (Sec. III-B).
 #include "sampler.hpp"
 #include "variants.hpp"
 
@@ -41,9 +45,10 @@ template <int P, int W>
 __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restrict__ xyz, int n,
                                                           int c, int start, int chunk,
                                                           int32_t* __restrict__ out, GridSync* gs,
-                                                          unsigned spin_limit) {
+                                                          unsigned spin_limit, unsigned* dev_status) {
     constexpr int T = 64 * W;
     __shared__ Candidate lds[2 * W];
+    __shared__ unsigned gave_up;   // a wave of this workgroup gave up waiting and returned
     const int G = gridDim.x;
     const int g = blockIdx.x;
     const int t = threadIdx.x;
@@ -52,6 +57,10 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
     const int first = g * chunk;
     const int cnt = min(chunk, n - first);
     const int ns = (cnt + T - 1) / T;
+    if (W > 1) {
+        if (t == 0) gave_up = 0u;
+        __syncthreads();
+    }
 
     float X[P], Y[P], Z[P];
     Dist<P, T, false> D;
@@ -61,10 +70,25 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
     // Picks are buffered one per lane (pick i in lane i mod 64); wave 0 of
     // workgroup 0 writes them 64 at a time.
     uint32_t picks = (uint32_t)start;
+    // Leave at iteration i without its pick: workgroup 0's wave 0 writes the
+    // buffered picks before i and -1 from i on.
+    auto leave = [&](int i) {
+        if (g == 0 && w == 0) {
+            const int done = i & ~63;   // picks before `done` are written
+            if (lane < (i & 63)) out[done + lane] = (int32_t)picks;
+            for (int j = i + lane; j < c; j += 64) out[j] = -1;
+        }
+    };
 
     for (int i = 1; i < c; ++i) {
         const Pick mine = update_and_pick<P, T, false>(ns, w, lane, X, Y, Z, D, px, py, pz);
         const Pick p = combine_waves<W>(mine, lds, i & 1, w, lane);
+        // After the exchange's barrier: a sibling that gave up has returned
+        // (and no longer writes its candidate), so this wave returns too.
+        if (W > 1 && __hip_atomic_load(&gave_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            leave(i);
+            return;
+        }
         const uint64_t tag = (uint64_t)(i & 0xFFFF);
         uint64_t* slots = gs->slot[i & 1];
         if (t == 0)
@@ -86,13 +110,16 @@ __global__ __launch_bounds__(64 * W) void fps_grid_kernel(const float* __restric
             __builtin_amdgcn_s_sleep(1);
         }
         if (!ok) {
-            if (lane == 0) __hip_atomic_store(&gs->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (g == 0 && w == 0) {
-                const int done = i & ~63;   // picks before `done` are written
-                if (lane < (i & 63)) out[done + lane] = (int32_t)picks;
-                for (int j = i + lane; j < c; j += 64) out[j] = -1;
+            if (lane == 0) {
+                __hip_atomic_store(&gs->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_or(dev_status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (W > 1) __hip_atomic_store(&gave_up, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            return;   // the wave's own exit; waves that still wait leave through their own polls
+            // the flag is in LDS before this wave ends (its siblings read it
+            // after their next barrier, which this wave no longer holds up)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            leave(i);
+            return;
         }
         const uint32_t d = lane < G ? (uint32_t)(v >> 32) : 0u;
         const uint32_t best = wave_max(d);

@@ -22,8 +22,14 @@
 // Allocation is serialised per workgroup by an LDS lock; frees are atomic
 // ANDs on the used-mask and need no lock.  Every wait (for the lock, or for
 // pages another wave of the workgroup still holds) polls at most spin_limit
-// times; a wave that gives up marks every sector still queued as failed
-// (outputs -1) so that no output is left unwritten, and exits.
+// times; a wave that gives up sets the plan's status word and the device's
+// failure word, marks every sector still queued as failed (outputs -1) so
+// that no output is left unwritten, and exits.
+//
+// With a stamp buffer (afps_plan_launch_stamped), lane 0 of each wave records
+// per sector the shader clock when it took the sector, when the sector was in
+// LDS and when its last pick was written (plus the constant-rate clock, for
+// the shader clock's rate): cycles per iteration measured on the device.
 #include "sampler.hpp"
 #include "variants.hpp"
 
@@ -67,40 +73,69 @@ __device__ __forceinline__ void fail_item(const WorkItem& wi, int32_t* out_all, 
 // Sample one sector with the NPDU variant its size calls for; `lds` is the
 // first of its pages.
 __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int32_t* __restrict__ out_all,
-                                         const WorkItem& wi, uint32_t* lds) {
+                                         const WorkItem& wi, uint32_t* lds, uint64_t* t_loaded) {
     const float* xyz = xyz_all + 3 * wi.xyz_offset;
     int32_t* out = out_all + wi.out_offset;
     switch (npdu_r_for(wi.n)) {
-        case 1: sample_sector_npdu<1, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
-        case 2: sample_sector_npdu<2, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
-        case 4: sample_sector_npdu<4, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
-        default: sample_sector_npdu<8, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags); break;
+        case 1: sample_sector_npdu<1, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
+        case 2: sample_sector_npdu<2, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
+        case 4: sample_sector_npdu<4, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
+        default: sample_sector_npdu<8, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
+    }
+}
+
+// run_item, timed into a.stamps[item] when the launch records stamps.
+__device__ __forceinline__ void run_stamped(const PoolArgs& a, int item, const WorkItem& wi, uint32_t* lds,
+                                            int lane) {
+    if (!a.stamps) {
+        run_item(a.xyz_all, a.out_all, wi, lds, nullptr);
+        return;
+    }
+    const uint64_t take_rt = __builtin_amdgcn_s_memrealtime();
+    const uint64_t take = __builtin_amdgcn_s_memtime();
+    uint64_t loaded = take;
+    run_item(a.xyz_all, a.out_all, wi, lds, &loaded);
+    const uint64_t end = __builtin_amdgcn_s_memtime();
+    const uint64_t end_rt = __builtin_amdgcn_s_memrealtime();
+    if (lane == 0) {
+        SectorStamp st;
+        st.take = take;
+        st.loaded = loaded;
+        st.end = end;
+        st.take_rt = take_rt;
+        st.end_rt = end_rt;
+        st.item = item;
+        st.n = wi.n;
+        st.c = wi.c;
+        st.k = wi.k;
+        // HW_ID (register 4) and XCC_ID (register 20), whole 32-bit registers
+        st.hw_id = (uint32_t)__builtin_amdgcn_s_getreg((31 << 11) | 4);
+        st.xcc_id = (uint32_t)__builtin_amdgcn_s_getreg((31 << 11) | 20);
+        a.stamps[item] = st;
     }
 }
 
 }  // namespace
 
 template <int W>
-__global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __restrict__ xyz_all,
-                                                             int32_t* __restrict__ out_all,
-                                                             const WorkItem* __restrict__ items,
-                                                             const PoolQueue* __restrict__ queues,
-                                                             int nq, unsigned* qtaken,
-                                                             const PoolSeed* __restrict__ seeds,
-                                                             int seed_groups, int pool_pages,
-                                                             unsigned spin_limit) {
+__global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
     static_assert(W <= kMaxPoolWaves, "seed table holds kMaxPoolWaves waves per workgroup");
     extern __shared__ __attribute__((aligned(16))) uint32_t pool[];
     __shared__ uint64_t used[3];
     __shared__ uint32_t lock;
     const int lane = threadIdx.x & 63;
-    const bool seeded = (int)blockIdx.x < seed_groups;
+    const int nq = a.nq;
+    const unsigned spin_limit = a.spin_limit;
+    const WorkItem* __restrict__ items = a.items;
+    const PoolQueue* __restrict__ queues = a.queues;
+    unsigned* qtaken = a.qtaken;
+    const bool seeded = (int)blockIdx.x < a.seed_groups;
     if (threadIdx.x < 3) {
         const int wd = (int)threadIdx.x, lo = 64 * wd;
-        uint64_t u = pool_pages <= lo ? ~0ull : (pool_pages >= lo + 64 ? 0ull : (~0ull << (pool_pages - lo)));
+        uint64_t u = a.pool_pages <= lo ? ~0ull : (a.pool_pages >= lo + 64 ? 0ull : (~0ull << (a.pool_pages - lo)));
         if (seeded)
             for (int w = 0; w < W; ++w) {
-                const PoolSeed sd = seeds[blockIdx.x * W + w];
+                const PoolSeed sd = a.seeds[blockIdx.x * W + w];
                 if (sd.item >= 0) u |= page_bits(wd, sd.page, npdu_pool_pages(items[sd.item].n));
             }
         used[wd] = u;
@@ -111,7 +146,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
     // ---- the wave's seed: pages already marked, no lock
     if (seeded) {
         const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        const PoolSeed sd = seeds[blockIdx.x * W + wv];
+        const PoolSeed sd = a.seeds[blockIdx.x * W + wv];
         if (sd.item >= 0) {
             for (int z = 0; z < sd.sleeps; ++z) __builtin_amdgcn_s_sleep(127);   // kSeedSleepCycles each
             const WorkItem wi = items[sd.item];
@@ -120,7 +155,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
             // of seeds takes the longest sectors): its instructions go first
             // when a SIMD has another wave ready too.
             if (wv == 0) __builtin_amdgcn_s_setprio(3);
-            run_item(xyz_all, out_all, wi, pool + sd.page * (kPoolPageBytes / 4));
+            run_stamped(a, sd.item, wi, pool + sd.page * (kPoolPageBytes / 4), lane);
             if (wv == 0) __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // this sector's accesses are done
             if (lane == 0)
@@ -168,7 +203,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
         const int r2 = free_run(2, lane, u0, u1, u2);
         const int longest = (int)wave_max((uint32_t)max(r0, max(r1, r2)));
 
-        // ---- first queue (highest priority) with sectors left that fit
+        // ---- first queue (highest priority) with sectors left that fits
         const unsigned t0 = q0 < nq ? __hip_atomic_load(&qtaken[q0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         const unsigned t1 = q1 < nq ? __hip_atomic_load(&qtaken[q1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         const bool left0 = t0 < (unsigned)count0, left1 = t1 < (unsigned)count1;
@@ -217,7 +252,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
         spins = 0;                                                // the limit bounds each wait
 
         const WorkItem wi = items[item];
-        run_item(xyz_all, out_all, wi, pool + s * (kPoolPageBytes / 4));
+        run_stamped(a, item, wi, pool + s * (kPoolPageBytes / 4), lane);
 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // this sector's accesses are done
         if (lane == 0) {
@@ -227,7 +262,11 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
         }
     }
     if (!failed) return;
-    // Gave up waiting: take every sector still queued and mark it failed.
+    // Gave up waiting: report it, take every sector still queued and mark it failed.
+    if (lane == 0) {
+        __hip_atomic_fetch_or(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(a.dev_status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     for (int q = 0; q < nq; ++q) {
         const PoolQueue Q = queues[q];
         for (;;) {
@@ -235,7 +274,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const float* __rest
             if (lane == 0) idx = atomicAdd(&qtaken[q], 1u);
             idx = (unsigned)__builtin_amdgcn_readfirstlane((int)idx);
             if (idx >= (unsigned)Q.count) break;
-            fail_item(items[Q.first + (int)idx], out_all, lane);
+            fail_item(items[Q.first + (int)idx], a.out_all, lane);
         }
     }
 }

@@ -359,7 +359,7 @@ template <bool SHIFT>
 __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restrict__ xyz, int n, int c,
                                                           int k, int cur, int base,
                                                           int32_t* __restrict__ out, uint32_t* lds,
-                                                          bool first_full) {
+                                                          bool first_full, uint64_t* t_loaded) {
     const int lane = threadIdx.x & 63;
     const int nb = (n + 63) >> 6;
     const int np = npdu_padded_points(n);
@@ -406,6 +406,7 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
         }
     }
     sector_lds_ready();
+    if (t_loaded) *t_loaded = __builtin_amdgcn_s_memtime();
 
     // Lanes past the last block hold 0: a lower lane holds a value >= 0, so
     // they never win the lowest-lane search below.  bi holds, per block, the
@@ -522,7 +523,7 @@ template <int R, bool XYZ_IN_LDS, bool SHIFT>
 __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restrict__ xyz, int n, int c,
                                                           int k, int cur, int base,
                                                           int32_t* __restrict__ out, uint32_t* lds,
-                                                          bool first_full) {
+                                                          bool first_full, uint64_t* t_loaded) {
     static_assert(R >= 1 && R <= 8 && (R & (R - 1)) == 0, "R is 1, 2, 4 or 8 block registers");
     // Coordinates read from global memory (XYZ_IN_LDS = false) go through a
     // buffer resource bounded to the sector's 12 n bytes: a block's two loads
@@ -578,6 +579,7 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
         for (int j = lane; j < np; j += 64) rec[j] = j < n ? init : 0u;
     }
     sector_lds_ready();
+    if (t_loaded) *t_loaded = __builtin_amdgcn_s_memtime();
 
     uint32_t bm[R], bi[R];   // block maxima and their positions inside the block
 #pragma unroll
@@ -781,6 +783,7 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
 //   cur   : local start point
 //   lds   : npdu_lds_words(n, XYZ_IN_LDS) words of shared memory
 //   flags : kNpduFirstFull, kNpduShiftEdges
+//   t_loaded: if not null, receives the shader clock once the sector is in LDS
 // The sector is cut into blocks of 64 consecutive points whose maxima (and
 // the lowest index reaching them) live one block per lane.  Distances only
 // decrease and only inside the window, so every other block keeps its
@@ -793,18 +796,20 @@ template <int R, bool XYZ_IN_LDS>
 __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz, int n, int c,
                                                    int k, int cur, int base,
                                                    int32_t* __restrict__ out, uint32_t* lds,
-                                                   int flags) {
+                                                   int flags, uint64_t* t_loaded = nullptr) {
     const bool first_full = (flags & kNpduFirstFull) != 0;
     const bool shift = (flags & kNpduShiftEdges) != 0;
     if constexpr (R == 1 && XYZ_IN_LDS) {
         if (k <= 64) {   // the window lies in two adjacent blocks
-            if (shift) sample_sector_npdu_narrow<true>(xyz, n, c, k, cur, base, out, lds, first_full);
-            else sample_sector_npdu_narrow<false>(xyz, n, c, k, cur, base, out, lds, first_full);
+            if (shift) sample_sector_npdu_narrow<true>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
+            else sample_sector_npdu_narrow<false>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
             return;
         }
     }
-    if (shift) sample_sector_npdu_blocks<R, XYZ_IN_LDS, true>(xyz, n, c, k, cur, base, out, lds, first_full);
-    else sample_sector_npdu_blocks<R, XYZ_IN_LDS, false>(xyz, n, c, k, cur, base, out, lds, first_full);
+    if (shift)
+        sample_sector_npdu_blocks<R, XYZ_IN_LDS, true>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
+    else
+        sample_sector_npdu_blocks<R, XYZ_IN_LDS, false>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
 }
 
 }  // namespace afps

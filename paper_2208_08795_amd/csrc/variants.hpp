@@ -92,6 +92,34 @@ static_assert(sizeof(PoolSeed) == 8, "pool seed layout");
 constexpr int kSeedSleepCycles = 127 * 64;   // one s_sleep(127)
 constexpr int kMaxPoolWaves = 8;
 constexpr int kMaxPoolSeedGroups = 512;
+// Timestamps of one sector of a pooled launch (afps_plan_launch_stamped):
+// the shader clock (s_memtime, cycles) when its wave took it, when its points
+// were in LDS and when its last pick was written; the constant-rate clock
+// (s_memrealtime) at take and end, which gives the shader clock's rate; the
+// wave's hardware id register (CU, SIMD, wave slot) and XCC id.
+struct SectorStamp {
+    uint64_t take, loaded, end;
+    uint64_t take_rt, end_rt;
+    int32_t item, n, c, k;
+    uint32_t hw_id, xcc_id;
+};
+static_assert(sizeof(SectorStamp) == 64, "sector stamp layout");
+
+// Arguments of the pooled NPDU kernel (passed by value).
+struct PoolArgs {
+    const float* xyz_all;
+    int32_t* out_all;
+    const WorkItem* items;
+    const PoolQueue* queues;
+    unsigned* qtaken;          // one counter per queue
+    const PoolSeed* seeds;
+    unsigned* status;          // the plan's status word (workspace), set when a wave gives up
+    unsigned* dev_status;      // the device's failure word, set alike
+    SectorStamp* stamps;       // per plan item, or nullptr
+    int nq, seed_groups, pool_pages;
+    unsigned spin_limit;
+};
+
 struct PoolEntry {
     int waves;
     const void* kernel;

@@ -8,7 +8,10 @@ sector counts), which the executor copies into the arena and samples with one
 batch-plan launch on one of several streams.  Batches launched while others
 are still running overlap on the device.  When a batch's completion event has
 fired, its frames are done (latency = completion - arrival, host clock) and
-their arena blocks are freed for the next admissions.
+their arena blocks are freed for the next admissions.  A frame's indices come
+back to the host with it (an asynchronous copy into a pinned mirror of the
+arena, ordered before the completion event); a frame whose indices hold -1
+(a kernel gave up a bounded wait, see afps_set_spin_limit) is "failed".
 
 The scheduler (admission, arena, bookkeeping) is plain host logic; the
 executor is the only part that touches the GPU, so the policy can be checked
@@ -195,9 +198,13 @@ class Scheduler:
         for batch in list(self.inflight):
             if self.ex.done(batch.handle):
                 t = self.clock()
-                self.ex.finish(batch)
+                failed = self.ex.finish(batch) or {}
                 for req in batch.requests:
-                    req.state, req.done = "done", t
+                    req.done = t
+                    if req.rid in failed:
+                        req.state, req.error = "failed", failed[req.rid]
+                    else:
+                        req.state = "done"
                     self.finished.append(req)
                 self._release(batch)
                 self.inflight.remove(batch)
@@ -238,10 +245,13 @@ class Scheduler:
 class GpuExecutor:
     """Copies a batch's frames into the device arena and samples them in one
     batch-plan launch (NPDU-AFPS / AFPS) or one launch per frame (plain FPS),
-    on one of `streams` HIP streams; completion is an event."""
+    on one of `streams` HIP streams, then copies each frame's indices into a
+    pinned host mirror of the arena; completion is an event.  `on_launch`, if
+    given, is called with (stream, batch) right after the sampling launches
+    (e.g. to record timing events around them)."""
 
     def __init__(self, arena_bytes: int, streams: int = 4, keep_results: bool = False,
-                 device="cuda"):
+                 device="cuda", on_launch=None):
         import torch
 
         from . import binding
@@ -249,9 +259,11 @@ class GpuExecutor:
         self.L = binding.lib()
         self.buf = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
         self.base = self.buf.data_ptr()
+        self.host = torch.empty(arena_bytes, dtype=torch.uint8, pin_memory=True)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.next = 0
         self.keep = keep_results
+        self.on_launch = on_launch
 
     def _points_view(self, req):
         t = self.torch
@@ -290,20 +302,34 @@ class GpuExecutor:
             for r in fps:
                 B._check(self.L.afps_fps_plain(ctypes.c_void_p(self.base + r.pts_off), r.n, r.c,
                                                r.start, ctypes.c_void_p(self.base + r.out_off), sh))
-            if self.keep:
-                for r in reqs:
-                    r.result = self._out_view(r).to("cpu", non_blocking=True)
+            if self.on_launch is not None:
+                self.on_launch(s, batch)
+            for r in reqs:
+                self._host_view(r).copy_(self._out_view(r), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
         return (ev, plan)
+
+    def _host_view(self, req):
+        return self.host[req.out_off:req.out_off + 4 * req.c].view(self.torch.int32)
 
     def done(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, batch: Batch):
+        """The batch's event has fired: destroy its plan and return
+        {rid: error} for the frames whose indices hold -1."""
         ev, plan = batch.handle
+        failed = {}
+        for r in batch.requests:
+            v = self._host_view(r).numpy()
+            if v.size and int(v.min()) < 0:
+                failed[r.rid] = "device-side failure: %d of %d indices are -1" % (int((v < 0).sum()), v.size)
+            if self.keep:
+                r.result = self.torch.from_numpy(v.copy())
         if plan is not None:
             self.L.afps_plan_destroy(plan)
+        return failed
 
 
 def latency_summary(finished):

@@ -83,6 +83,11 @@ def test_host_validation_without_gpu(L):
     assert L.afps_tune_set(100, 1, 1, 1) == -2   # NPDU is not tuned
     assert L.afps_tune_set(100, 0, 1, 1) == -2   # 64 points: too small for 100
     assert L.afps_max_sector_points() == 32768
+    # plan calls without a plan, stamps or workspace are rejected on the host
+    assert L.afps_plan_launch_noalloc(None, dummy, dummy, None) == -1
+    assert L.afps_plan_status(None, dummy, None) == -1
+    assert L.afps_plan_launch_stamped(None, dummy, dummy, dummy, dummy, 64, None) == -1
+    assert L.afps_noalloc_max_items() == ((1 << 20) - 35584) // 40
     # grouping: arguments checked on the host; no centres launches nothing
     assert L.afps_ball_query(None, 10, dummy, 4, 1.0, 8, -1, dummy, None, None) == -1
     assert L.afps_ball_query(dummy, 10, None, 4, 1.0, 8, -1, dummy, None, None) == -1

@@ -1,0 +1,107 @@
+"""GPU tests of the batch entry points around the plan calls: the one-shot
+afps_batched, the binding's batched() on the default and an explicit stream
+(eager and graph), and the stamped launch whose per-sector timestamps give
+cycles per iteration; every index against the oracle (tolerance 0)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_08795_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_08795_amd import binding
+    binding.lib()
+    return torch, binding, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def batch256():
+    clouds = synth.batch_of_objects(256, seed=0)
+    cs = [len(p) // 4 for p in clouds]
+    want = [oracle.afps(p, c, 8, 32, 0) for p, c in zip(clouds, cs)]
+    return clouds, cs, want
+
+
+def test_one_shot_afps_batched_on_the_batch_of_256(env, batch256):
+    torch, B, dev = env
+    clouds, cs, want = batch256
+    sizes = [len(p) for p in clouds]
+    print("afps_batched: 256 clouds, %d points" % sum(sizes), flush=True)
+    xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    for stream in (None, torch.cuda.Stream(device=dev)):
+        if stream is not None:
+            stream.wait_stream(torch.cuda.current_stream())
+        out = B.batched_oneshot(xyz, sizes, cs, [8] * 256, [32] * 256, [0] * 256, stream=stream)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        o = 0
+        for i, c in enumerate(cs):
+            assert np.array_equal(got[o:o + c], want[i]), (stream is not None, i)
+            o += c
+
+
+def test_one_shot_rejects_bad_descriptors_without_launching(env):
+    torch, B, dev = env
+    xyz = torch.zeros((100, 3), dtype=torch.float32, device=dev)
+    out = torch.full((70,), -7, dtype=torch.int32, device=dev)
+    with pytest.raises(B.AfpsError) as e:
+        B.batched_oneshot(xyz, [50, 50], [10, 60], [1, 1], [None, 4], [0, 0], out_all=out)
+    assert e.value.status == -2
+    torch.cuda.synchronize()
+    assert bool((out == -7).all())
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("explicit_stream", [False, True])
+def test_binding_batched_streams(env, batch256, graph, explicit_stream):
+    torch, B, dev = env
+    clouds, cs, want = batch256
+    print("binding.batched graph=%s explicit_stream=%s" % (graph, explicit_stream), flush=True)
+    tensors = [torch.from_numpy(p).to(dev) for p in clouds]
+    stream = torch.cuda.Stream(device=dev) if explicit_stream else None
+    res = B.batched(tensors, cs, [8] * 256, [32] * 256, graph=graph, stream=stream)
+    # results are ready on the current stream without a further synchronisation
+    host = [r.cpu().numpy() for r in res]
+    for i, w in enumerate(want):
+        assert np.array_equal(host[i], w), i
+
+
+def test_stamped_launch_is_exact_and_its_stamps_are_consistent(env, batch256):
+    torch, B, dev = env
+    clouds, cs, want = batch256
+    sizes = [len(p) for p in clouds]
+    plan = B.BatchPlan(sizes, cs, [8] * 256, [32] * 256, [0] * 256, device=dev)
+    xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    print("stamped launch: %d items" % plan.items, flush=True)
+    out, stamps = plan.launch_stamped(xyz)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i, w in enumerate(want):
+        o = plan.offsets[i]
+        assert np.array_equal(got[o:o + cs[i]], w), i
+    st = stamps.cpu().numpy()
+    pairs = st[:, 5:8].copy().view(np.int32).reshape(-1, 6)   # item, n, c, k, hw_id, xcc_id
+    take, loaded, end, take_rt, end_rt = (st[:, j] for j in range(5))
+    assert np.array_equal(pairs[:, 0], np.arange(plan.items))          # every item stamped once
+    assert sorted(pairs[:, 1].tolist()) == sorted(
+        n // 8 + (s < n % 8) for n in sizes for s in range(8))        # its sector's points
+    assert np.all(pairs[:, 3] == 32)
+    assert np.all(take <= loaded) and np.all(loaded <= end) and np.all(take_rt < end_rt)
+    # the shader clock's rate from the two counters: a plausible engine clock
+    khz = int(B.lib().afps_wall_clock_khz())
+    assert khz > 0
+    ghz = (end - take).sum() / (end_rt - take_rt).sum() * khz * 1e-6
+    print("shader clock from stamps: %.3f GHz" % ghz, flush=True)
+    assert 0.5 < ghz < 3.0
+    many = pairs[:, 2] > 1
+    cyc = (end - loaded)[many] / (pairs[many, 2] - 1)
+    print("cycles per iteration: median %.0f, max %.0f" % (np.median(cyc), cyc.max()), flush=True)
+    assert 100 < np.median(cyc) < 5000
+    plan.close()

@@ -467,6 +467,7 @@ def test_grid_barrier_timeout_is_bounded(B, torch_dev):
     torch, dev = torch_dev
     pts = synth.lidar_scan(800, seed=1, n=50000)
     xyz = torch.from_numpy(pts).to(dev)
+    B.clear_device_status()
     B.set_spin_limit(1)
     try:
         out = B.fps(xyz, 400, 0)
@@ -480,6 +481,16 @@ def test_grid_barrier_timeout_is_bounded(B, torch_dev):
     f = int(bad[0]) if bad.size else len(got)
     assert np.array_equal(got[:f], want[:f])
     assert np.all(got[f:] == -1)
+    # the give-up is reported (AFPS_ERR_DEVICE) until cleared; then a normal run is exact and clean
+    if bad.size:
+        with pytest.raises(B.AfpsError) as e:
+            B.device_status()
+        assert e.value.status == -7
+    B.clear_device_status()
+    out = B.fps(xyz, 400, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    B.device_status()
 
 
 def test_pool_wait_timeout_fails_whole_sectors_and_resets(B, torch_dev):
@@ -494,11 +505,14 @@ def test_pool_wait_timeout_fails_whole_sectors_and_resets(B, torch_dev):
     plan = B.BatchPlan([len(p) for p in clouds], cs, m, [32] * len(clouds), [0] * len(clouds), device=dev)
     xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
     want = [oracle.afps(p, c, 8, 32, 0) for p, c in zip(clouds, cs)]
+    failed_sectors = 0
+    B.clear_device_status()
     try:
         B.set_spin_limit(1)
         out = plan.launch(xyz)
         torch.cuda.synchronize()
         got = out.cpu().numpy()
+        failed_sectors = int((got == -1).sum())
         for i, (c, w) in enumerate(zip(cs, want)):
             g = got[plan.offsets[i]:plan.offsets[i] + c]
             qn, rn, qc, rc = len(clouds[i]) // 8, len(clouds[i]) % 8, c // 8, c % 8
@@ -508,12 +522,21 @@ def test_pool_wait_timeout_fails_whole_sectors_and_resets(B, torch_dev):
                 assert np.array_equal(sector, w[o:o + cc]) or np.all(sector == -1), (i, s)
     finally:
         B.set_spin_limit(1 << 22)
+    # a launch with -1 sectors reports AFPS_ERR_DEVICE, through the plan and the device
+    if failed_sectors:
+        for check in (plan.status, B.device_status):
+            with pytest.raises(B.AfpsError) as e:
+                check()
+            assert e.value.status == -7
+    B.clear_device_status()
     for graph in (False, True):
         out = plan.launch(xyz, graph=graph)
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         for i, (c, w) in enumerate(zip(cs, want)):
             assert np.array_equal(got[plan.offsets[i]:plan.offsets[i] + c], w), (graph, i)
+        plan.status()                 # each launch clears the plan's word
+    B.device_status()
     plan.close()
 
 

@@ -51,3 +51,49 @@ def test_served_in_mix_equals_alone(fps):
     for r in sorted(done, key=lambda r: r.rid)[:3]:
         want = oracle.afps(frames[r.rid].points, r.c, r.m, r.k, r.start)
         assert np.array_equal(r.result.numpy(), want), "oracle frame %d" % r.rid
+
+
+def test_frames_with_failed_sectors_are_marked_failed():
+    """A frame whose indices come back holding -1 ends "failed", every other
+    frame is exact (equal to the frame sampled alone): first with one frame's
+    indices overwritten with -1 on the launch stream (as a kernel that gave up
+    leaves them), then with a spin limit of 1, under which waves of the pooled
+    kernel may give up their waits."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_08795_amd import binding
+    from paper_2208_08795_amd.serve import GpuExecutor, Scheduler
+    frames = synth.frame_stream(rate=5000.0, count=16, seed=8, n_min=16384, n_max=60000)
+    budget = 12 << 20
+
+    def spoil(stream, batch):
+        for r in batch.requests:
+            if r.rid == 3:
+                ex._out_view(r)[r.c // 2:].fill_(-1)   # on `stream`, the executor's current stream
+
+    for spin_one in (False, True):
+        reqs = _requests(torch, frames)
+        ex = GpuExecutor(budget, streams=2, keep_results=True, on_launch=None if spin_one else spoil)
+        s = Scheduler(ex, budget, max_inflight=2, max_batch=8)
+        print("serving 16 frames, %s" % ("spin limit 1" if spin_one else "frame 3 spoiled"), flush=True)
+        if spin_one:
+            binding.set_spin_limit(1)
+        try:
+            done = s.run(reqs)
+            torch.cuda.synchronize()
+        finally:
+            binding.set_spin_limit(1 << 22)
+            binding.clear_device_status()
+        states = {r.rid: r.state for r in done}
+        print("failed frames:", sorted(k for k, v in states.items() if v == "failed"), flush=True)
+        assert len(done) == 16 and set(states.values()) <= {"done", "failed"}
+        if not spin_one:
+            assert [k for k, v in states.items() if v == "failed"] == [3]
+        for r in done:
+            x = torch.from_numpy(frames[r.rid].points).cuda()
+            alone = binding.afps_npdu(x, r.c, r.m, r.k, r.start).cpu().numpy()
+            if r.state == "failed":
+                assert "-1" in r.error and (r.result.numpy() == -1).any()
+            else:
+                assert np.array_equal(r.result.numpy(), alone), "frame %d" % r.rid

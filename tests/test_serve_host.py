@@ -15,10 +15,12 @@ class FakeClock:
 
 
 class FakeExecutor:
-    """A batch takes 1 ms per frame; launches of frames in fail_ids raise."""
+    """A batch takes 1 ms per frame; launches of frames in fail_ids raise;
+    frames in device_fail_ids complete with a device-side failure."""
 
-    def __init__(self, clock, fail_ids=()):
+    def __init__(self, clock, fail_ids=(), device_fail_ids=()):
         self.clock, self.fail_ids = clock, set(fail_ids)
+        self.device_fail_ids = set(device_fail_ids)
         self.launched = []
         self.live_bytes = []
 
@@ -35,7 +37,7 @@ class FakeExecutor:
         return self.clock.t >= handle
 
     def finish(self, batch):
-        pass
+        return {r.rid: "device-side failure: -1 indices" for r in batch.requests if r.rid in self.device_fail_ids}
 
 
 def _req(i, n, arrival, m=8, k=64):
@@ -120,3 +122,17 @@ def test_workspace_block_covers_large_batches():
     assert all(r.state == "done" for r in done)
     assert max(len(b) for b in ex.launched) >= 16
     assert library_workspace_bytes(32 * 16) > 256 + 32 * 32 * 16     # 40 bytes per sector
+
+
+def test_device_side_failure_marks_only_its_frames_failed():
+    clock = FakeClock()
+    s = Scheduler(FakeExecutor(clock, device_fail_ids={2, 5}), 16 << 20, max_batch=3, clock=clock)
+    reqs = [_req(i, 40000, 0.0003 * i) for i in range(9)]
+    done = {r.rid: r for r in s.run(reqs)}
+    assert {i for i, r in done.items() if r.state == "failed"} == {2, 5}
+    assert all("-1" in done[i].error for i in (2, 5))
+    assert all(done[i].state == "done" for i in range(9) if i not in (2, 5))
+    assert s.arena.bytes_used == 0
+    from paper_2208_08795_amd.serve import latency_summary
+    summ = latency_summary(list(done.values()))
+    assert summ["failed"] == 2 and summ["frames"] == 7
