@@ -298,7 +298,39 @@ int afps_batched(const float *xyz_all, const afps_cloud_desc *descs, int32_t bat
 enum { AFPS_TUNE_DIRECT = 0, AFPS_TUNE_NPDU = 1, AFPS_TUNE_BATCH = 2 };
 int afps_tune_get(int32_t n_s, int32_t kind, int32_t *waves, int32_t *slots);
 int afps_tune_set(int32_t n_s_max, int32_t kind, int32_t waves, int32_t slots);
-void afps_tune_reset(void);
+void afps_tune_reset(void);   /* forgets every tuned entry and the pool policy (not the occupancy) */
+
+/*
+ * NPDU placement in batch plans created afterwards: NPDU sectors of at most
+ * n_s_max points with windows k <= k_max keep their coordinates in LDS
+ * (xyz_in_lds = 1: 16-byte records {D, x, y, z}, possible up to 8192 points)
+ * or read them from L2 (0: only the distances take LDS, 4 bytes per point, so
+ * a pooled CU holds four times the sectors).  The entry with the smallest
+ * n_s_max (then k_max) that covers a sector decides; without one, sectors up
+ * to 8192 points keep their coordinates in LDS.  Read from AFPS_TUNE_CACHE
+ * as lines "npdu n_s_max k_max xyz_in_lds".  AFPS_ERR_ARG for bad values.
+ * afps_npdu_xyz_in_lds reports the placement a sector would get.
+ */
+int afps_tune_npdu(int32_t n_s_max, int32_t k_max, int32_t xyz_in_lds);
+int afps_npdu_xyz_in_lds(int32_t n_s, int32_t k);
+
+/*
+ * Policy of the pooled NPDU launch of batch plans created afterwards:
+ *   waves, groups_per_cu  the launch shape: 4 or 8 waves per workgroup and 1
+ *                         or 2 workgroups per CU, each owning that share of
+ *                         the CU's LDS pages (used when every sector fits the
+ *                         share); 0, 0 = chosen from the plan's occupancy
+ *                         budget and its sectors (afps_set_plan_occupancy)
+ *   seed_sleep            1 = first sectors with slack before the plan's
+ *                         longest one wait a sleep period before loading
+ *   seed_priority         issue priority 0..3 of the wave running its
+ *                         workgroup's first (longest) seed
+ * Read from AFPS_TUNE_CACHE as a line "pool waves groups sleep priority".
+ * Defaults 0, 0, 1, 3; afps_tune_reset restores them.  AFPS_ERR_ARG for
+ * values outside these sets.
+ */
+int afps_set_pool_policy(int32_t waves, int32_t groups_per_cu, int32_t seed_sleep,
+                         int32_t seed_priority);
 
 /*
  * Run one sector variant explicitly (for the autotuner and tests): AFPS or

@@ -69,6 +69,9 @@ def lib():
             "afps_device_status": ([vp, i32], ctypes.c_int),
             "afps_init": ([], ctypes.c_int),
             "afps_wall_clock_khz": ([], i32),
+            "afps_tune_npdu": ([i32, i32, i32], ctypes.c_int),
+            "afps_npdu_xyz_in_lds": ([i32, i32], ctypes.c_int),
+            "afps_set_pool_policy": ([i32, i32, i32, i32], ctypes.c_int),
             "afps_noalloc_max_items": ([], i32),
             "afps_plan_items": ([vp], i32),
             "afps_plan_launches": ([vp], i32),
@@ -457,3 +460,18 @@ def tune_set(n_s_max: int, waves: int, slots: int, kind: int = TUNE_DIRECT):
 
 def tune_reset():
     lib().afps_tune_reset()
+
+
+def tune_npdu(n_s_max: int, k_max: int, xyz_in_lds: bool):
+    """Coordinates of NPDU sectors of at most n_s_max points (windows k <= k_max)
+    in LDS or read from L2, for batch plans created afterwards."""
+    _check(lib().afps_tune_npdu(n_s_max, k_max, 1 if xyz_in_lds else 0))
+
+
+def npdu_xyz_in_lds(n_s: int, k: int) -> bool:
+    return bool(lib().afps_npdu_xyz_in_lds(n_s, k))
+
+
+def set_pool_policy(waves: int = 0, groups: int = 0, seed_sleep: bool = True, seed_priority: int = 3):
+    """Shape and seeding of the pooled NPDU launch of batch plans created afterwards."""
+    _check(lib().afps_set_pool_policy(waves, groups, 1 if seed_sleep else 0, seed_priority))

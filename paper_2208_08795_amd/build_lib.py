@@ -30,6 +30,7 @@ def _units():
               ("fps_grid.hip", "fps_grid.o", []), ("check.hip", "check.o", []),
               ("binning.hip", "binning.o", []),
               ("group.hip", "group.o", []),
+              ("planner.cpp", "planner.o", []),
               ("afps_api.cpp", "afps_api.o", ["-x", "hip"])]
     return units
 

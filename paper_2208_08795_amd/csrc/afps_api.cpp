@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "afps.h"
+#include "planner.hpp"
 #include "variants.hpp"
 
 using namespace afps;
@@ -102,6 +103,20 @@ struct Tuned {
 std::mutex g_tune_mu;
 std::vector<Tuned> g_tuned[2];
 bool g_tune_loaded = false;
+// Policy of pooled NPDU launches in batch plans (occupancy budget, shape,
+// seeding, coordinate placement); guarded by g_tune_mu.
+PoolPolicy g_pool_policy;
+
+void sort_placement(std::vector<NpduPlacement>& tab) {
+    std::sort(tab.begin(), tab.end(), [](const NpduPlacement& a, const NpduPlacement& b) {
+        return a.n_max != b.n_max ? a.n_max < b.n_max : a.k_max < b.k_max;
+    });
+}
+
+bool valid_pool_policy(int waves, int groups, int sleep, int prio) {
+    const bool shape = (waves == 0 && groups == 0) || ((waves == 4 || waves == 8) && (groups == 1 || groups == 2));
+    return shape && (sleep == 0 || sleep == 1) && prio >= 0 && prio <= 3;
+}
 
 void load_tune_file_locked() {
     if (g_tune_loaded) return;
@@ -110,17 +125,34 @@ void load_tune_file_locked() {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    // lines: "<direct|batch> <n_max> <waves> <slots>"
+    // lines: "<direct|batch> <n_max> <waves> <slots>", "npdu <n_max> <k_max> <xyz_in_lds>",
+    //        "pool <waves> <groups> <seed_sleep> <seed_priority>"
     char kind[16];
-    int n_max, waves, slots;
-    while (std::fscanf(f, "%15s %d %d %d", kind, &n_max, &waves, &slots) == 4) {
+    while (std::fscanf(f, "%15s", kind) == 1) {
+        int a = 0, b = 0, c = 0, d = 0;
+        if (std::strcmp(kind, "pool") == 0) {
+            if (std::fscanf(f, "%d %d %d %d", &a, &b, &c, &d) != 4) break;
+            if (valid_pool_policy(a, b, c, d)) {
+                g_pool_policy.waves = a;
+                g_pool_policy.groups = b;
+                g_pool_policy.seed_sleep = c != 0;
+                g_pool_policy.seed_priority = d;
+            }
+            continue;
+        }
+        if (std::fscanf(f, "%d %d %d", &a, &b, &c) != 3) break;
+        if (std::strcmp(kind, "npdu") == 0) {
+            if (a >= 1 && b >= 0 && (c == 0 || c == 1)) g_pool_policy.placement.push_back({a, b, c});
+            continue;
+        }
         const int t = std::strcmp(kind, "direct") == 0 ? 0 : std::strcmp(kind, "batch") == 0 ? 1 : -1;
-        const VariantEntry* v = find_full(waves, slots);
-        if (t >= 0 && v && capacity(*v) >= n_max) g_tuned[t].push_back({n_max, waves, slots});
+        const VariantEntry* v = find_full(b, c);
+        if (t >= 0 && v && capacity(*v) >= a) g_tuned[t].push_back({a, b, c});
     }
     std::fclose(f);
     for (auto& tab : g_tuned)
-        std::sort(tab.begin(), tab.end(), [](const Tuned& a, const Tuned& b) { return a.n_max < b.n_max; });
+        std::sort(tab.begin(), tab.end(), [](const Tuned& x, const Tuned& y) { return x.n_max < y.n_max; });
+    sort_placement(g_pool_policy.placement);
 }
 
 // Variant for a full-update sector of n points; batch = persistent launch.
@@ -136,6 +168,17 @@ const VariantEntry* choose_full(int n, bool batch = false) {
             }
     }
     return rule_full(n);
+}
+
+// The batch (persistent) variant of a full-update sector of n points.
+bool batch_variant(int n, FullVariantInfo* out) {
+    const VariantEntry* v = n <= kMaxFullSector ? choose_full(n, true) : nullptr;
+    if (!v) return false;
+    out->id = (int)(v - registry().full.data());
+    out->waves = v->waves;
+    out->slots = v->slots;
+    out->lds_bytes = v->lds_bytes;
+    return true;
 }
 
 const NpduEntry* choose_npdu(int n) {
@@ -254,32 +297,15 @@ int helper_streams(DeviceState* d) {
 // ------------------------------------------------------------ validation
 
 int check_sizes(int32_t n, int32_t c, int32_t m, int32_t start) {
-    if (m < 1 || c < m || n < c)
-        return fail(AFPS_ERR_ARG, "sizes must satisfy 1 <= m <= c <= n (n=" + std::to_string(n) +
-                                      ", c=" + std::to_string(c) + ", m=" + std::to_string(m) + ")");
-    if (start < 0 || start >= n)
-        return fail(AFPS_ERR_RANGE, "start " + std::to_string(start) + " outside [0, n)");
-    return AFPS_OK;
+    std::string e;
+    const int rc = afps::check_sizes(n, c, m, start, &e);
+    return rc ? fail(rc, e) : AFPS_OK;
 }
 
-int32_t largest_sector(int32_t n, int32_t m) { return n / m + (n % m ? 1 : 0); }
-
-// Windows wider than twice the sector behave exactly like 2*n_s (the window
-// then spans the sector from any sample); clamping keeps index sums in range.
-int32_t clamp_k(int32_t k, int32_t n_s) { return k > 2 * n_s ? 2 * n_s : k; }
-
-// NPDU reading flags: checked, and k counting the sample turned into the same
-// window one smaller (the kernels implement the other two readings).
 int npdu_readings(int32_t* k, int32_t* flags) {
-    if (*flags & ~(AFPS_NPDU_FIRST_FULL | AFPS_NPDU_SHIFT_EDGES | AFPS_NPDU_K_WITH_SELF))
-        return fail(AFPS_ERR_ARG, "unknown NPDU reading flags");
-    if (*flags && *k < 0) return fail(AFPS_ERR_ARG, "NPDU reading flags need NPDU (k >= 0)");
-    if (*flags & AFPS_NPDU_K_WITH_SELF) {
-        if (*k < 1) return fail(AFPS_ERR_ARG, "k must be >= 1 when it counts the sample");
-        *k -= 1;
-        *flags &= ~AFPS_NPDU_K_WITH_SELF;
-    }
-    return AFPS_OK;
+    std::string e;
+    const int rc = afps::npdu_readings(k, flags, &e);
+    return rc ? fail(rc, e) : AFPS_OK;
 }
 
 // ------------------------------------------------------------ launches
@@ -301,11 +327,6 @@ int launch_npdu_direct(const NpduEntry& v, const float* xyz, int32_t n, int32_t 
 }
 
 unsigned g_spin_limit = 1u << 22;
-
-// Optional wave budget of batch plans, in waves per SIMD; 0 = none (every
-// persistent grid is as large as fits, at most one workgroup per item, which
-// measured fastest on the batched workloads).
-float g_waves_per_simd = 0.0f;
 
 // Validate inputs before every sampling call (AFPS_CHECK=1 in the
 // environment at load, or afps_set_checking).
@@ -567,14 +588,51 @@ int afps_tune_set(int32_t n_s_max, int32_t kind, int32_t waves, int32_t slots) {
 void afps_tune_reset(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& tab : g_tuned) tab.clear();
+    const float occupancy = g_pool_policy.waves_per_simd;
+    g_pool_policy = PoolPolicy();
+    g_pool_policy.waves_per_simd = occupancy;
     g_tune_loaded = true;   // forget the cache file too
 }
 
 int afps_set_plan_occupancy(float waves_per_simd) {
     if (!(waves_per_simd >= 0.0f) || waves_per_simd > 64.0f)
         return fail(AFPS_ERR_ARG, "waves per SIMD must be 0 (no budget) or in (0, 64]");
-    g_waves_per_simd = waves_per_simd;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_pool_policy.waves_per_simd = waves_per_simd;
     return AFPS_OK;
+}
+
+int afps_tune_npdu(int32_t n_s_max, int32_t k_max, int32_t xyz_in_lds) {
+    if (n_s_max < 1 || k_max < 0 || (xyz_in_lds != 0 && xyz_in_lds != 1))
+        return fail(AFPS_ERR_ARG, "need n_s_max >= 1, k_max >= 0 and xyz_in_lds 0 or 1");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
+    auto& tab = g_pool_policy.placement;
+    tab.erase(std::remove_if(tab.begin(), tab.end(),
+                             [&](const NpduPlacement& e) { return e.n_max == n_s_max && e.k_max == k_max; }),
+              tab.end());
+    tab.push_back({n_s_max, k_max, xyz_in_lds});
+    sort_placement(tab);
+    return AFPS_OK;
+}
+
+int afps_set_pool_policy(int32_t waves, int32_t groups_per_cu, int32_t seed_sleep, int32_t seed_priority) {
+    if (!valid_pool_policy(waves, groups_per_cu, seed_sleep, seed_priority))
+        return fail(AFPS_ERR_ARG, "pool shape must be (0, 0) or waves 4|8 and groups 1|2; seed_sleep 0|1; "
+                                  "seed_priority 0..3");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
+    g_pool_policy.waves = waves;
+    g_pool_policy.groups = groups_per_cu;
+    g_pool_policy.seed_sleep = seed_sleep != 0;
+    g_pool_policy.seed_priority = seed_priority;
+    return AFPS_OK;
+}
+
+int afps_npdu_xyz_in_lds(int32_t n_s, int32_t k) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
+    return npdu_xyz_in_lds(g_pool_policy, n_s, k) ? 1 : 0;
 }
 
 size_t afps_bin_workspace_bytes(int32_t n, int32_t bins) {
@@ -663,44 +721,19 @@ int afps_set_spin_limit(uint32_t polls) {
 
 // ================================================================ batch plans
 
-namespace {
-
-struct Bucket {
-    const void* kernel;   // persistent kernel
-    int block;            // threads per workgroup
-    int lds_bytes;        // dynamic LDS
-    int first, count;     // items [first, first + count) of the plan
-    int grid;             // workgroups launched
-    double cost;          // estimated work (cycles of one workgroup), for ordering and sizing
-    double longest;       // estimated cycles of the bucket's longest item
-    bool pool;            // the pooled NPDU kernel (queues below, not one counter)
-};
-
-// Workspace of a plan: [bucket counters | pool queue counters | pool queue
-// table | pool seeds | work items].
-constexpr size_t kCounterBytes = 256;                                   // one per bucket, then the status word
-constexpr int kStatusWord = (int)(kCounterBytes / sizeof(unsigned)) - 1; // set by a launch whose wait gave up
-constexpr int kMaxBuckets = kStatusWord;
-constexpr size_t kPoolCounterOffset = kCounterBytes;                    // one per pool queue
-constexpr size_t kPoolTableOffset = kPoolCounterOffset + kMaxPoolQueues * sizeof(unsigned);
-constexpr size_t kPoolSeedOffset = kPoolTableOffset + kMaxPoolQueues * sizeof(PoolQueue);
-constexpr size_t kItemsOffset = kPoolSeedOffset + (size_t)kMaxPoolSeedGroups * kMaxPoolWaves * sizeof(PoolSeed);
-static_assert(kItemsOffset % 256 == 0, "work items start 256-byte aligned");
-constexpr int kResetWords = (int)(kPoolTableOffset / sizeof(unsigned));
-
-// Estimated cycles of one NPDU iteration (one wave, window of two blocks).
-constexpr double kNpduIterCycles = 650.0;
-
-}  // namespace
-
+// A batch plan: the planner's tables (host logic, planner.cpp) plus the
+// kernels they map to and the HIP objects of its launches.
 struct afps_plan {
     std::vector<WorkItem> items;
-    std::vector<Bucket> buckets;
+    std::vector<PlannedBucket> buckets;
+    std::vector<const void*> kernels;  // the kernel of each bucket
     std::vector<PoolQueue> queues;    // pool queues, highest priority first
     std::vector<PoolSeed> seeds;      // first sector of each pool wave (workgroup-major)
     std::vector<CheckSeg> clouds;     // each descriptor's points, for the optional input check
     int pool_pages = 0;               // LDS pages of one pooled workgroup
     int pool_groups = 0;              // pooled workgroups per CU (1 or 2; 0 without NPDU sectors)
+    int pool_waves = 0;
+    int seed_priority = 0;
     size_t ws_bytes = 0;
     int device = 0;
     std::vector<hipEvent_t> events;   // fork / join events (1 + helper streams)
@@ -723,260 +756,62 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     if (!plan_out || (!descs && batch > 0)) return fail(AFPS_ERR_NULL, "descs and plan must be non-null");
     *plan_out = nullptr;
     if (batch < 0) return fail(AFPS_ERR_ARG, "batch must be >= 0");
+    // Validation and sector expansion first (host only): a bad descriptor is
+    // reported before anything touches a device.
+    PlannerEnv env;
+    env.cu_count = 1;
+    env.cu_pool_pages = kMaxPoolPages;
+    PlanTables pre;
+    std::string err;
+    env.choose_full = [](int n, FullVariantInfo* v) { return batch_variant(n, v); };
+    env.blocks_per_cu = [](const FullVariantInfo&) { return 1; };
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file_locked();
+        env.pool = g_pool_policy;
+    }
+    int rc = build_plan(descs, batch, env, &pre, &err);
+    if (rc && rc != AFPS_ERR_UNSUPPORTED) return fail(rc, err);
     std::unique_ptr<afps_plan> plan(new afps_plan());
-
-    struct Staged {
-        WorkItem item;
-        const void* kernel;   // full-update variant; nullptr = NPDU (pooled)
-        int block, lds;       // full-update: workgroup size and dynamic LDS
-        int pages;            // NPDU: pool pages
-        double cost;
-    };
-    std::vector<Staged> staged;
-    for (int32_t b = 0; b < batch; ++b) {
-        const afps_cloud_desc& d = descs[b];
-        const std::string where = "descriptor " + std::to_string(b) + ": ";
-        if (d.xyz_offset < 0 || d.out_offset < 0) return fail(AFPS_ERR_ARG, where + "negative offset");
-        int rc = check_sizes(d.n, d.c, d.m, d.start);
-        if (rc) return fail(rc, where + g_last_error);
-        int32_t dk = d.k, dflags = d.flags;
-        if ((rc = npdu_readings(&dk, &dflags))) return fail(rc, where + g_last_error);
-        plan->clouds.push_back(CheckSeg{d.xyz_offset, d.n, 0});
-        const int32_t qn = d.n / d.m, rn = d.n % d.m, qc = d.c / d.m, rc_ = d.c % d.m;
-        for (int32_t s = 0; s < d.m; ++s) {
-            Staged st{};
-            WorkItem& it = st.item;
-            const int32_t ns = qn + (s < rn ? 1 : 0), bs = s * qn + std::min(s, rn);
-            const int32_t cs = qc + (s < rc_ ? 1 : 0), os = s * qc + std::min(s, rc_);
-            it.xyz_offset = d.xyz_offset + bs;
-            it.out_offset = d.out_offset + os;
-            it.n = ns;
-            it.c = cs;
-            it.k = dk < 0 ? -1 : clamp_k(dk, ns);
-            it.start = d.start % ns;
-            it.base = bs;
-            it.flags = dflags;
-            if (dk >= 0) {
-                if (npdu_r_for(ns) == 0) return fail(AFPS_ERR_UNSUPPORTED, where + "NPDU sector too large");
-                st.kernel = nullptr;
-                st.pages = npdu_pool_pages(ns);
-                // iterations of the window update; sectors whose window spans
-                // more than two blocks re-reduce one more block per extra 64
-                st.cost = (double)cs * kNpduIterCycles * (1.0 + std::max(0, it.k - 64) / 128.0);
-            } else {
-                const VariantEntry* v = ns <= kMaxFullSector ? choose_full(ns, true) : nullptr;
-                if (!v)
-                    return fail(AFPS_ERR_UNSUPPORTED,
-                                where + "sector of " + std::to_string(ns) +
-                                    " points exceeds one workgroup (split into more sectors)");
-                st.kernel = v->persistent;
-                st.block = 64 * v->waves;
-                st.lds = v->lds_bytes;
-                // per iteration: 12 VALU ops per slot on each of the ceil(W/4)
-                // waves sharing a SIMD (4 cycles each), plus the reduction
-                // and, for W > 1, the LDS exchange
-                const int per_simd = (v->waves + 3) / 4;
-                st.cost = (double)cs * (48.0 * v->slots * per_simd + (v->waves > 1 ? 600.0 : 250.0));
-            }
-            staged.push_back(st);
-        }
-    }
     DeviceState* ds = nullptr;
-    if (!staged.empty()) {
-        int rc = device_state(&ds);
-        if (rc) return rc;
+    if (batch > 0) {
+        if ((rc = device_state(&ds))) return rc;
         AFPS_HIP(hipGetDevice(&plan->device));
-        plan->pool_pages = ds->pool_pages;
+        env.cu_count = ds->cu_count;
+        env.cu_pool_pages = ds->pool_pages;
     }
-
-    // NPDU sectors: one pool bucket.  Queues by page count, each longest
-    // first; queues ordered by their longest sector.
-    std::vector<Staged> npdu, full;
-    for (auto& st : staged) (st.kernel ? full : npdu).push_back(st);
-    std::stable_sort(npdu.begin(), npdu.end(), [](const Staged& a, const Staged& b) {
-        if (a.pages != b.pages) return a.pages > b.pages;
-        return a.cost > b.cost;
-    });
-    std::vector<std::pair<double, std::pair<int, int>>> qorder;   // (longest cost, [first, count))
-    for (size_t i = 0; i < npdu.size();) {
-        size_t j = i;
-        while (j < npdu.size() && npdu[j].pages == npdu[i].pages) ++j;
-        if (npdu[i].pages > plan->pool_pages)
-            return fail(AFPS_ERR_UNSUPPORTED, "NPDU sector of " + std::to_string(npdu[i].item.n) +
-                                                  " points exceeds the LDS of one CU");
-        qorder.push_back({npdu[i].cost, {(int)i, (int)(j - i)}});
-        i = j;
-    }
-    if ((int)qorder.size() > kMaxPoolQueues) return fail(AFPS_ERR_UNSUPPORTED, "too many NPDU sector sizes");
-    std::stable_sort(qorder.begin(), qorder.end(),
-                     [](const auto& a, const auto& b) { return a.first > b.first; });
-
-    // Full-update sectors: one bucket per (kernel, LDS), longest first inside.
-    std::stable_sort(full.begin(), full.end(), [](const Staged& a, const Staged& b) {
-        if (a.kernel != b.kernel) return a.kernel < b.kernel;
-        if (a.lds != b.lds) return a.lds < b.lds;
-        return a.cost > b.cost;
-    });
-
-    plan->items.reserve(staged.size());
-    if (!npdu.empty()) {
-        Bucket bk{nullptr, 0, 0, 0, 0, 0, 0.0, 0.0, true};
-        std::vector<double> npdu_cost;   // estimated cycles, aligned with the items
-        for (const auto& q : qorder) {
-            const int first = (int)plan->items.size();
-            for (int i = 0; i < q.second.second; ++i) {
-                const Staged& st = npdu[q.second.first + i];
-                plan->items.push_back(st.item);
-                npdu_cost.push_back(st.cost);
-                bk.cost += st.cost;
-                bk.longest = std::max(bk.longest, st.cost);
-            }
-            plan->queues.push_back({first, q.second.second, npdu[q.second.first].pages, 0});
-        }
-        bk.count = (int)plan->items.size();
-        // Waves per CU: one per SIMD keeps the longest sectors at full speed;
-        // two per SIMD give more throughput (about 1.7x) when the batch is
-        // bound by total work rather than by its longest sector.
-        const double cus = (double)ds->cu_count;
-        const double span4 = std::max(bk.longest, bk.cost / (4.0 * cus));
-        const double span8 = std::max(1.18 * bk.longest, bk.cost / (6.8 * cus));
-        int waves = span8 < span4 ? 8 : 4;
-        if (g_waves_per_simd > 0.0f) waves = g_waves_per_simd < 1.5f ? 4 : 8;
-        // Two waves per SIMD run as two workgroups of four per CU, each owning
-        // half of the CU's pages, whenever every sector fits half: one launch
-        // runs as fast either way, but a launch then gives its LDS back half
-        // a CU at a time, so a launch queued behind it on another stream
-        // starts sooner.
-        int max_pages = 0;
-        for (const auto& q : plan->queues) max_pages = std::max(max_pages, q.pages);
-        plan->pool_groups = waves == 8 && max_pages <= plan->pool_pages / 2 ? 2 : 1;
-        if (plan->pool_groups == 2) {
-            waves = 4;
-            plan->pool_pages /= 2;
-        }
-        const PoolEntry* pe = nullptr;
-        for (const auto& v : registry().pool)
-            if (v.waves == waves) pe = &v;
-        if (!pe) return fail(AFPS_ERR_UNSUPPORTED, "pooled NPDU kernel missing");
-        bk.kernel = pe->kernel;
-        bk.block = 64 * pe->waves;
-        bk.lds_bytes = plan->pool_pages * kPoolPageBytes;
-        bk.grid = std::min(plan->pool_groups * ds->cu_count, bk.count);
-        // Seeds: the queue policy of the kernel played out on the host for
-        // the moment every wave starts (wave w of every workgroup, then wave
-        // w + 1, each taking the first queue with sectors left that fits its
-        // workgroup's pages), so that a launch starts without a rush of every
-        // wave on the same queue counter.  A workgroup's seeds sit in
-        // consecutive pages from page 0; the seeded sectors are the front of
-        // their queues, which then start after them.  Seeds after the first
-        // round whose estimated cost leaves room before the plan's longest
-        // item wait one sleep period before loading: the first round (the
-        // longest sectors) then loads with less competition for bandwidth,
-        // and the wait cannot lengthen the launch by the cost model.
-        const int sg = std::min(bk.grid, kMaxPoolSeedGroups);
-        plan->seeds.assign((size_t)sg * pe->waves, PoolSeed{-1, 0, 0});
-        std::vector<int> taken(plan->queues.size(), 0), used(sg, 0);
-        for (int w = 0; w < pe->waves; ++w)
-            for (int g = 0; g < sg; ++g)
-                for (size_t q = 0; q < plan->queues.size(); ++q) {
-                    const PoolQueue& Q = plan->queues[q];
-                    if (taken[q] < Q.count && used[g] + Q.pages <= plan->pool_pages) {
-                        const int item = Q.first + taken[q];
-                        const bool slack = w > 0 && npdu_cost[item] + kSeedSleepCycles <= bk.longest;
-                        plan->seeds[(size_t)g * pe->waves + w] =
-                            PoolSeed{item, (int16_t)used[g], (int16_t)(slack ? 1 : 0)};
-                        used[g] += Q.pages;
-                        ++taken[q];
-                        break;
-                    }
-                }
-        for (size_t q = 0; q < plan->queues.size(); ++q) {
-            plan->queues[q].first += taken[q];
-            plan->queues[q].count -= taken[q];
-        }
-        plan->buckets.push_back(bk);
-    }
-    std::vector<double> item_cost(plan->items.size(), 0.0);   // estimated cycles, aligned with items
-    for (size_t i = 0; i < full.size();) {
-        size_t j = i;
-        Bucket bk{full[i].kernel, full[i].block, full[i].lds, (int)plan->items.size(), 0, 0, 0.0, 0.0, false};
-        while (j < full.size() && full[j].kernel == bk.kernel && full[j].lds == bk.lds_bytes) {
-            bk.cost += full[j].cost;
-            bk.longest = std::max(bk.longest, full[j].cost);
-            plan->items.push_back(full[j].item);
-            item_cost.push_back(full[j].cost);
-            ++j;
-        }
-        bk.count = (int)(j - i);
-        plan->buckets.push_back(bk);
-        i = j;
-    }
-    if ((int)plan->buckets.size() > kMaxBuckets) return fail(AFPS_ERR_UNSUPPORTED, "too many kernel variants in one plan");
-    // Largest bucket first: it gets the first helper stream.
-    std::stable_sort(plan->buckets.begin(), plan->buckets.end(),
-                     [](const Bucket& a, const Bucket& b) { return a.cost > b.cost; });
-
-    // Full-update persistent grids: as many workgroups as stay resident, at
-    // most one per item.
-    if (!plan->buckets.empty()) {
-        // Makespan model: the queue hands out items longest first, so a
-        // bucket run by g workgroups finishes when the longest-processing-
-        // time (LPT) schedule of its item costs on g machines does.  Take
-        // the critical path T = the longest item of the plan, give each
-        // bucket the fewest workgroups whose LPT schedule ends by T, and
-        // raise T until all buckets together stay within the wave budget
-        // (waves per SIMD x SIMDs).  Never more workgroups than items or
-        // than fit.
-        const double budget = std::max(1.0, (double)g_waves_per_simd * 4.0 * ds->cu_count);
-        std::vector<int> cap(plan->buckets.size());
-        double T = 0.0;
-        for (size_t b = 0; b < plan->buckets.size(); ++b) {
-            Bucket& bk = plan->buckets[b];
-            T = std::max(T, bk.longest);
-            if (bk.pool) continue;
-            int per_cu = 0;
-            AFPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bk.kernel, bk.block, bk.lds_bytes));
-            if (per_cu < 1) return fail(AFPS_ERR_UNSUPPORTED, "a kernel variant cannot be resident");
-            cap[b] = std::min(bk.count, per_cu * ds->cu_count);
-        }
-        auto lpt_makespan = [&](const Bucket& bk, int g) {
-            std::vector<double> load(g, 0.0);   // min-heap of machine loads
-            double span = 0.0;
-            for (int i = 0; i < bk.count; ++i) {
-                std::pop_heap(load.begin(), load.end(), std::greater<double>());
-                load.back() += item_cost[bk.first + i];
-                span = std::max(span, load.back());
-                std::push_heap(load.begin(), load.end(), std::greater<double>());
-            }
-            return span;
-        };
-        auto workgroups_for = [&](size_t b, double T) {
-            const Bucket& bk = plan->buckets[b];
-            int lo = (int)std::min<double>(cap[b], std::max(1.0, std::ceil(bk.cost / T)));
-            int hi = cap[b];
-            if (lpt_makespan(bk, lo) <= T * 1.0001) return lo;
-            while (lo + 1 < hi) {                 // smallest g in (lo, hi] meeting T
-                const int mid = lo + (hi - lo) / 2;
-                if (lpt_makespan(bk, mid) <= T * 1.0001) hi = mid;
-                else lo = mid;
-            }
-            return hi;
-        };
-        if (g_waves_per_simd <= 0.0f) {
-            for (size_t b = 0; b < plan->buckets.size(); ++b)
-                if (!plan->buckets[b].pool) plan->buckets[b].grid = cap[b];
+    env.blocks_per_cu = [](const FullVariantInfo& v) {
+        int per_cu = 0;
+        const VariantEntry& e = registry().full[v.id];
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e.persistent, 64 * e.waves, e.lds_bytes) !=
+            hipSuccess)
+            return 0;
+        return per_cu;
+    };
+    PlanTables t;
+    if ((rc = build_plan(descs, batch, env, &t, &err))) return fail(rc, err);
+    plan->items = std::move(t.items);
+    plan->buckets = std::move(t.buckets);
+    plan->queues = std::move(t.queues);
+    plan->seeds = std::move(t.seeds);
+    plan->clouds = std::move(t.clouds);
+    plan->pool_pages = t.pool_pages;
+    plan->pool_groups = t.pool_groups;
+    plan->pool_waves = t.pool_waves;
+    plan->seed_priority = t.seed_priority;
+    plan->ws_bytes = t.ws_bytes;
+    for (const auto& bk : plan->buckets) {
+        const void* k = nullptr;
+        if (bk.pool()) {
+            for (const auto& v : registry().pool)
+                if (v.waves == plan->pool_waves) k = v.kernel;
         } else {
-            for (int round = 0; round < 200; ++round) {
-                double waves = 0.0;
-                for (size_t b = 0; b < plan->buckets.size(); ++b) {
-                    Bucket& bk = plan->buckets[b];
-                    if (!bk.pool) bk.grid = workgroups_for(b, T);
-                    waves += (double)bk.grid * (bk.block / 64);
-                }
-                if (waves <= budget) break;
-                T *= 1.05;
-            }
+            k = registry().full[bk.variant].persistent;
         }
+        if (!k) return fail(AFPS_ERR_UNSUPPORTED, "a planned kernel is not built");
+        plan->kernels.push_back(k);
+    }
+    if (!plan->buckets.empty()) {
         if (plan->buckets.size() > 1) {
             int hrc = helper_streams(ds);   // created outside any stream capture
             if (hrc) return hrc;
@@ -988,28 +823,18 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
             plan->events.push_back(e);
         }
     }
-    plan->ws_bytes = afps_workspace_bytes_for_items((int32_t)plan->items.size());
     *plan_out = plan.release();
     return AFPS_OK;
 }
 
 size_t afps_plan_workspace_bytes(const afps_plan* plan) { return plan ? plan->ws_bytes : 0; }
 
-size_t afps_workspace_bytes_for_items(int32_t items) {
-    if (items <= 0) return 0;
-    const size_t b = kItemsOffset + (size_t)items * sizeof(WorkItem);
-    return (b + 255) / 256 * 256;
-}
+size_t afps_workspace_bytes_for_items(int32_t items) { return workspace_bytes_for_items(items); }
 int32_t afps_plan_items(const afps_plan* plan) { return plan ? (int32_t)plan->items.size() : 0; }
 
 int32_t afps_plan_launches(const afps_plan* plan) { return plan ? (int32_t)plan->buckets.size() : 0; }
 
-int32_t afps_plan_pool_waves(const afps_plan* plan) {
-    if (!plan) return 0;
-    for (const auto& bk : plan->buckets)
-        if (bk.pool) return bk.block / 64;
-    return 0;
-}
+int32_t afps_plan_pool_waves(const afps_plan* plan) { return plan ? plan->pool_waves : 0; }
 
 int32_t afps_plan_pool_groups_per_cu(const afps_plan* plan) { return plan ? plan->pool_groups : 0; }
 
@@ -1074,8 +899,9 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
     AFPS_HIP(hipLaunchKernel(queue_reset_kernel(), dim3(1), dim3(kResetWords), rargs, 0, stream));
 
     auto launch_bucket = [&](int b, hipStream_t s) -> int {
-        const Bucket& bk = plan->buckets[b];
-        if (bk.pool) {
+        const PlannedBucket& bk = plan->buckets[b];
+        const void* kernel = plan->kernels[b];
+        if (bk.pool()) {
             PoolArgs pa{};
             pa.xyz_all = xyz_all;
             pa.out_all = out_all;
@@ -1090,15 +916,16 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
             pa.seed_groups = (int)plan->seeds.size() / (bk.block / 64);
             pa.pool_pages = plan->pool_pages;
             pa.spin_limit = g_spin_limit;
+            pa.seed_priority = plan->seed_priority;
             void* args[] = {&pa};
-            AFPS_HIP(hipLaunchKernel(bk.kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
+            AFPS_HIP(hipLaunchKernel(kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
             return AFPS_OK;
         }
         const WorkItem* first = items + bk.first;
         int count = bk.count;
         unsigned* counter = counters + b;
         void* args[] = {(void*)&xyz_all, (void*)&out_all, (void*)&first, (void*)&count, (void*)&counter};
-        AFPS_HIP(hipLaunchKernel(bk.kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
+        AFPS_HIP(hipLaunchKernel(kernel, dim3(bk.grid), dim3(bk.block), args, bk.lds_bytes, s));
         return AFPS_OK;
     };
     if (nb == 1) return launch_bucket(0, stream);

@@ -70,17 +70,30 @@ __device__ __forceinline__ void fail_item(const WorkItem& wi, int32_t* out_all, 
     for (int j = lane; j < wi.c; j += 64) out[j] = -1;
 }
 
-// Sample one sector with the NPDU variant its size calls for; `lds` is the
-// first of its pages.
+// Pages a work item's sector occupies (its coordinates in LDS or not).
+__device__ __forceinline__ int item_pages(const WorkItem& wi) {
+    return npdu_pool_pages(wi.n, npdu_item_xyz_in_lds(wi.n, wi.flags));
+}
+
+// Sample one sector with the NPDU variant its size and coordinate placement
+// call for; `lds` is the first of its pages.
 __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int32_t* __restrict__ out_all,
                                          const WorkItem& wi, uint32_t* lds, uint64_t* t_loaded) {
     const float* xyz = xyz_all + 3 * wi.xyz_offset;
     int32_t* out = out_all + wi.out_offset;
+    const int f = wi.flags & ~kItemXyzInL2;
+    const bool in_lds = npdu_item_xyz_in_lds(wi.n, wi.flags);
     switch (npdu_r_for(wi.n)) {
-        case 1: sample_sector_npdu<1, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
-        case 2: sample_sector_npdu<2, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
-        case 4: sample_sector_npdu<4, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
-        default: sample_sector_npdu<8, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, wi.flags, t_loaded); break;
+        case 1:
+            if (in_lds) sample_sector_npdu<1, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
+            else sample_sector_npdu<1, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
+            break;
+        case 2:
+            if (in_lds) sample_sector_npdu<2, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
+            else sample_sector_npdu<2, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
+            break;
+        case 4: sample_sector_npdu<4, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded); break;
+        default: sample_sector_npdu<8, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded); break;
     }
 }
 
@@ -136,7 +149,7 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
         if (seeded)
             for (int w = 0; w < W; ++w) {
                 const PoolSeed sd = a.seeds[blockIdx.x * W + w];
-                if (sd.item >= 0) u |= page_bits(wd, sd.page, npdu_pool_pages(items[sd.item].n));
+                if (sd.item >= 0) u |= page_bits(wd, sd.page, item_pages(items[sd.item]));
             }
         used[wd] = u;
     }
@@ -150,13 +163,20 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
         if (sd.item >= 0) {
             for (int z = 0; z < sd.sleeps; ++z) __builtin_amdgcn_s_sleep(127);   // kSeedSleepCycles each
             const WorkItem wi = items[sd.item];
-            const int p = npdu_pool_pages(wi.n);
+            const int p = item_pages(wi);
             // Wave 0's seed is its workgroup's longest sector (the first round
-            // of seeds takes the longest sectors): its instructions go first
-            // when a SIMD has another wave ready too.
-            if (wv == 0) __builtin_amdgcn_s_setprio(3);
+            // of seeds takes the longest sectors): with a seed priority, its
+            // instructions go first when a SIMD has another wave ready too.
+            const bool raise = wv == 0 && a.seed_priority > 0;
+            if (raise) {
+                switch (a.seed_priority) {
+                    case 1: __builtin_amdgcn_s_setprio(1); break;
+                    case 2: __builtin_amdgcn_s_setprio(2); break;
+                    default: __builtin_amdgcn_s_setprio(3); break;
+                }
+            }
             run_stamped(a, sd.item, wi, pool + sd.page * (kPoolPageBytes / 4), lane);
-            if (wv == 0) __builtin_amdgcn_s_setprio(0);
+            if (raise) __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");   // this sector's accesses are done
             if (lane == 0)
                 for (int wd = 0; wd < 3; ++wd) {

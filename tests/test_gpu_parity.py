@@ -556,3 +556,49 @@ def test_autotuner_choices_stay_exact(B, torch_dev):
         _batch_case(B, torch, dev, clouds, [50, 64, 700, 750], [1] * 4, [None] * 4, [0, 1, 2, 3])
     finally:
         B.tune_reset()
+
+
+@pytest.mark.parametrize("placement", ["all_l2", "l2_up_to_2048", "l2_above_2048"])
+def test_pooled_sectors_with_tuned_coordinate_placement(B, torch_dev, placement):
+    """NPDU sectors whose coordinates the tuning table sends to L2 (only the
+    distances in LDS) in one pooled launch with sectors that keep them in
+    LDS: sizes on both sides of every threshold, every reading, windows inside
+    two blocks and wider; every index against the oracle, graph replays."""
+    torch, dev = torch_dev
+    B.tune_reset()
+    try:
+        if placement == "all_l2":
+            B.tune_npdu(8192, 1 << 30, False)
+        elif placement == "l2_up_to_2048":
+            B.tune_npdu(2048, 1 << 30, False)
+        else:
+            B.tune_npdu(2048, 1 << 30, True)
+            B.tune_npdu(8192, 1 << 30, False)
+        assert B.npdu_xyz_in_lds(1000, 32) == (placement == "l2_above_2048")
+        assert B.npdu_xyz_in_lds(5000, 32) == False
+        sizes = [4096, 4097, 2048, 2049, 8192, 777, 65, 1, 3000, 6000, 12000, 1500]
+        ms = [1, 1, 1, 1, 1, 1, 1, 1, 2, 3, 2, 1]
+        ks = [32, 64, 8, 100, 32, 0, 65, 0, 200, 17, 33, 64]
+        cs = [max(m, n // 5) for n, m in zip(sizes, ms)]
+        starts = [0, 4096, 7, 2048, 8191, 3, 64, 0, 2999, 5, 11999, 700]
+        flags = [0, 1, 2, 3, 0, 2, 0, 0, 1, 0, 2, 3]
+        clouds = [synth.object_cloud(n, seed=i) if i % 2 else synth.uniform_cube(n, seed=i) for i, n in enumerate(sizes)]
+        _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=2, flags=flags)
+    finally:
+        B.tune_reset()
+
+
+@pytest.mark.parametrize("shape", [(4, 1), (8, 1), (4, 2)])
+@pytest.mark.parametrize("seeding", [(False, 0), (True, 3)])
+def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
+    """Every pooled launch shape and seeding policy the tuner can pick, on
+    uneven clouds of the batch workload: indices equal the oracle's."""
+    torch, dev = torch_dev
+    clouds = synth.batch_of_objects(40, seed=21, n_min=1024, n_max=32768)
+    cs = [len(p) // 4 for p in clouds]
+    B.set_pool_policy(shape[0], shape[1], seeding[0], seeding[1])
+    try:
+        plan = _batch_case(B, torch, dev, clouds, cs, [8] * 40, [32] * 40, [0] * 40, graph_replays=1)
+        assert (plan.pool_waves, plan.pool_groups) == shape
+    finally:
+        B.tune_reset()
