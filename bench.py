@@ -2,22 +2,30 @@
 
 One step = one pass of the whole sampling path over one batch: 256 object-like
 clouds of uneven size (N log-uniform in [1024, 32768], C = N/4), AFPS with
-M = 8 sectors and NPDU window k = 32, all 2048 sectors in one persistent
-launch (queue reset + persistent kernel, replayed from a hipGraph).  Inputs are
-resident in HBM before the timed region.  The same 256 clouds are also sampled
-with plain FPS (one workgroup per cloud) for comparison.
+M = 8 sectors and NPDU window k = 32 (2048 sectors).  The K timed steps are one
+pooled launch of K rounds of that batch (afps_plan_launch_rounds: a stream of
+batches processed back to back on the device; the rounds alternate over two
+resident copies of the input and each writes its own output), bracketed by
+synchronisations; the same launch's HIP-event duration is the roofline's time
+basis, so `value` and `roofline` share one clock.  Inputs are resident in HBM
+before the timed region.  The same 256 clouds are also sampled with plain FPS.
 
-Prints ONE JSON line (rank 0, N = 1).  Extra fields: plain-FPS figures, per-step
-latency percentiles, single-cloud latencies of the paper-sized configurations,
-coverage radius against plain FPS, the roofline of the dominant kernel and the
-oracle's CPU baseline.
+Prints ONE JSON line (rank 0, N = 1).  Extra fields: one step's own latency,
+device-measured cycles per iteration (per-sector timestamps), plain-FPS
+figures with their roofline, single-cloud latencies of the paper-sized
+configurations, coverage radius against plain FPS, the serving streams with
+their p50/p99 and the served launches' roofline, and the oracle's CPU
+baseline.
 """
 from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import hashlib
 import json
+import math
 import os
+import subprocess
 import sys
 import time
 
@@ -28,11 +36,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "sampled pts/s + p50/p99 frame latency, AFPS-NPDU vs plain FPS, 1 MI355X"
-# MI355X peaks used for the roofline.
+# MI355X figures for the rooflines.
 HBM_PEAK_GBS = 8000.0
+CUS, SIMDS_PER_CU = 256, 4
 # fp32 VALU without FMA and without packed ops (the method's distance is a
 # chain of separately rounded sub/mul/add): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+VALU_PEAK_TOPS = CUS * SIMDS_PER_CU * 16 * 2.4e9 / 1e12
+PEAK_CLOCK_GHZ = 2.4
+# LDS bytes a CU serves per clock on 128-bit reads, measured with a
+# microbenchmark on MI355X (every wave of eight workgroups per CU reading
+# conflict-free 1 KB rows; see the LDS section of the design notes).
+LDS_BYTES_PER_CLK_PER_CU = 128.0
+# A wave64 VALU instruction occupies its SIMD's vector ALU for 4 cycles.
+VALU_CYCLES_PER_INST = 4
+# Bytes one LDS instruction of the NPDU loop moves, on average over its mix per
+# iteration (one broadcast 16-byte read of the sample, two 16-byte reads of a
+# window block each, one paired 4-byte write of the window's distances:
+# 1024 + 2 x 1024 + 512 bytes of lanes in 4 instructions).
+LDS_BYTES_PER_INST = (1024 + 2 * 1024 + 512) / 4
 
 
 def log(msg):
@@ -43,67 +64,25 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def time_steps(torch, plans, xyz_all, outs, steps, warmup, streams):
-    """Warm up, then time exactly `steps` graph launches, nothing else between
-    the two synchronisations.  Step i runs on stream i mod S with plan and
-    output i mod S (each plan has its own workspace), so a step starts on the
-    compute units the previous one has already finished with; every stream's
-    output is checked against the first afterwards.  Returns (wall seconds,
-    warm-up steps done)."""
-    S = len(plans)
-    done = max(warmup, S)                   # every plan's graph captured before timing
-    for i in range(done):
-        plans[i % S].launch(xyz_all, out_all=outs[i % S], graph=True, stream=streams[i % S])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        plans[i % S].launch(xyz_all, out_all=outs[i % S], graph=True, stream=streams[i % S])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for o in outs[1:]:
-        if not torch.equal(o, outs[0]):
-            raise SystemExit("bench: the pipelined streams' outputs differ")
-    return wall, done
-
-
-def step_latency(torch, plan, xyz_all, out, reps, stream):
-    """One step's own latency: graph launches one at a time on one stream,
-    HIP events around each."""
-    plan.launch(xyz_all, out_all=out, graph=True, stream=stream)
-    torch.cuda.synchronize()
+def _event_ms(torch, run, stream, reps):
+    """HIP-event durations (ms) of `reps` calls of run() on `stream`, one at a time."""
     ms = []
     for _ in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        plan.launch(xyz_all, out_all=out, graph=True, stream=stream)
+        run()
         b.record(stream)
         b.synchronize()
         ms.append(a.elapsed_time(b))
     return ms
 
 
-def time_kernel(torch, plan, xyz_all, out, reps, stream):
-    """Duration of the plan's kernels alone: eager launches (queue reset + the
-    persistent launch, no graph), HIP events on the launch stream."""
-    plan.launch(xyz_all, out_all=out, graph=False, stream=stream)
-    torch.cuda.synchronize()
-    ms = []
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        plan.launch(xyz_all, out_all=out, graph=False, stream=stream)
-        b.record(stream)
-        b.synchronize()
-        ms.append(a.elapsed_time(b))
-    return ms
-
-
-def npdu_work(sizes, cs, out_np, offsets, m, k):
-    """Algorithmic work of AFPS-NPDU, counted from the picks: for every
-    iteration of every sector, 9 fp32 ops per distance update of the window
-    (3 sub, 3 mul, 2 add, 1 min) and one compare per sector point for the
-    argmax the method defines.  Returns (ops, distance updates)."""
-    ops = upd = 0
+def npdu_counts(sizes, cs, out_np, offsets, m, k):
+    """Work of one pass of AFPS-NPDU over the batch, counted from its picks:
+    distance updates (the exact window sizes), iterations, the window and
+    block-maximum compares of the argmax (k + 1 + ceil(n_s / 64) per
+    iteration) and the compares of an Algorithm-1 scan ((c_s - 1) n_s)."""
+    upd = iters = win_cmp = blk_cmp = scan_cmp = 0
     for n, c, o in zip(sizes, cs, offsets):
         qn, rn, qc, rc = n // m, n % m, c // m, c % m
         for s in range(m):
@@ -112,10 +91,62 @@ def npdu_work(sizes, cs, out_np, offsets, m, k):
             cur = out_np[o + oo:o + oo + cc - 1].astype(np.int64) - b
             lo = np.maximum(0, cur - k // 2)
             hi = np.minimum(ns - 1, cur + (k - k // 2))
-            u = int((hi - lo + 1).sum())
-            upd += u
-            ops += 9 * u + (cc - 1) * ns
-    return ops, upd
+            upd += int((hi - lo + 1).sum())
+            iters += cc - 1
+            win_cmp += (cc - 1) * (k + 1)
+            blk_cmp += (cc - 1) * (-(-ns // 64))
+            scan_cmp += (cc - 1) * ns
+    return {"updates": upd, "iterations": iters, "ops": 9 * upd + win_cmp + blk_cmp,
+            "alg1_scan_ops": 9 * upd + scan_cmp}
+
+
+def fps_ops(sizes, cs):
+    """Plain FPS: every point updated and compared once per iteration."""
+    upd = sum((c - 1) * n for n, c in zip(sizes, cs))
+    return 9 * upd + upd, upd
+
+
+def counter_record(label):
+    """Per-round SQ / traffic counters of the pooled kernel in `label`'s launch
+    layout from the committed rocprofv3 record, or None when the kernel
+    sources changed since or that layout was not profiled."""
+    path = os.path.join(ROOT, "profiles", "pooled_npdu_kernel_batch256_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = "".join(open(os.path.join(ROOT, s)).read() for s in rec["sources"])
+    if hashlib.sha256(src.encode()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec.get("kernels", {}).get(label)
+
+
+def stamp_cycles(stamps, wall_khz):
+    """Device-measured cycles per iteration from one stamped launch: per
+    sector (end - loaded) / (c - 1) on the shader clock, the shader clock's
+    rate from the constant-rate counter, and the critical sector."""
+    st = stamps.cpu().numpy()
+    pairs = st[:, 5:8].copy().view(np.int32).reshape(-1, 6)   # item, n, c, k, hw_id, xcc_id
+    take, loaded, end, take_rt, end_rt = (st[:, j].astype(np.float64) for j in range(5))
+    n, c = pairs[:, 1], pairs[:, 2]
+    ok = c > 1
+    cyc = (end - loaded)[ok] / (c[ok] - 1)
+    ghz = float((end - take).sum() / (end_rt - take_rt).sum() * wall_khz * 1e-6) if wall_khz else None
+    crit = int(np.argmax(end - take.min()))
+    return {"median": round(float(np.median(cyc)), 1), "p10": round(float(np.percentile(cyc, 10)), 1),
+            "p90": round(float(np.percentile(cyc, 90)), 1),
+            "critical_sector": {"points": int(n[crit]), "samples": int(c[crit]),
+                                "cycles_per_iteration": round(float((end[crit] - loaded[crit]) / max(1, c[crit] - 1)), 1),
+                                "load_us": round(float((loaded[crit] - take[crit]) / (ghz * 1e3)), 2) if ghz else None,
+                                "ends_at_us": round(float((end[crit] - take.min()) / (ghz * 1e3)), 1) if ghz else None},
+            "by_points": {label: round(float(np.median(cyc[(n[ok] > lo) & (n[ok] <= hi)])), 1)
+                          for label, lo, hi in (("<=1024", 0, 1024), ("1025-2048", 1024, 2048),
+                                                ("2049-4096", 2048, 4096))
+                          if ((n[ok] > lo) & (n[ok] <= hi)).any()},
+            "sclk_ghz": round(ghz, 4) if ghz else None,
+            "what": "shader-clock cycles per iteration of each NPDU sector of one pass, from s_memtime stamps "
+                    "when the sector was in LDS and when its last pick was written; clock rate from "
+                    "s_memrealtime"}
 
 
 def single_cloud_latency(torch, binding, synth, stream, reps=20):
@@ -157,9 +188,6 @@ def single_cloud_latency(torch, binding, synth, stream, reps=20):
     return res
 
 
-CLOCK_GHZ = 2.4   # MI355X peak engine clock (SQ counters measured 2.41 GHz under these kernels)
-
-
 def _median_ms(torch, run, stream, reps):
     run()
     torch.cuda.synchronize()
@@ -174,10 +202,11 @@ def _median_ms(torch, run, stream, reps):
     return float(np.median(ts))
 
 
-def object_sweep(torch, binding, synth, stream, reps=10):
+def object_sweep(torch, binding, synth, stream, clock_ghz, reps=10):
     """Object cloud N=8192, C=2048: plain FPS, AFPS for M in {1..32}, NPDU at
     k in {8, 32, 128}: time per call (median), cycles per iteration of the
-    longest sector, coverage radius relative to plain FPS.  Then the
+    longest sector (call time at the measured shader clock, launch included),
+    coverage radius relative to plain FPS.  Then the
     alternative NPDU readings at k in {8, 32}, M in {1, 8}."""
     from paper_2208_08795_amd.quality import coverage_radius
     pts = synth.object_cloud(8192, 0)
@@ -198,7 +227,7 @@ def object_sweep(torch, binding, synth, stream, reps=10):
                 ref = r
             iters = -(-2048 // m) - 1
             rows.append({"m": m, "k": k, "ms": round(ms, 4), "sampled_pts_per_s": 2048 / (ms / 1e3),
-                         "cycles_per_iteration": round(ms * 1e-3 * CLOCK_GHZ * 1e9 / iters, 1),
+                         "cycles_per_iteration": round(ms * 1e-3 * clock_ghz * 1e9 / iters, 1),
                          "coverage_radius": round(r, 5), "coverage_vs_fps": round(r / ref, 4)})
     log("object sweep: " + ", ".join("M%d/k%s %.3fms r%.2f" % (x["m"], x["k"], x["ms"], x["coverage_vs_fps"])
                                      for x in rows))
@@ -303,64 +332,6 @@ def sortedness(torch, binding, synth, stream, reps=10):
                     "on the same order; binning: shuffled LiDAR frames, points in binned order written"}
 
 
-def serving(torch, rates=(50, 200, 800), frames_npdu=160, frames_fps=24, pool=48, seed=1):
-    """Open-loop Poisson streams of LiDAR frames (N uniform in [16384, 131072],
-    C = N/8, M in {8, 16, 32}, k = 64) through the continuous-batching server,
-    AFPS-NPDU and plain FPS, per-frame latency from arrival to completion."""
-    from paper_2208_08795_amd import synth
-    from paper_2208_08795_amd.serve import GpuExecutor, Request, Scheduler, latency_summary
-    rng = np.random.default_rng(seed)
-    log("generating %d serving frames" % pool)
-    frames = synth.frame_stream(rate=1.0, count=pool, seed=seed)
-    pinned = [torch.from_numpy(f.points).pin_memory() for f in frames]
-    budget = 256 << 20
-    ex = GpuExecutor(budget, streams=4)
-    res = {"budget_bytes": budget, "frames": "pool of %d distinct synthetic 64-beam frames, N uniform "
-                                                "in [16384, 131072], C = N/8, M in {8,16,32}, k = 64" % pool}
-
-    def stream(method, count, lam):
-        gaps = rng.exponential(1.0 / lam, count)
-        arr = np.cumsum(gaps) - gaps[0]
-        reqs = []
-        for i in range(count):
-            f = frames[i % pool]
-            m, k = (f.m, f.k) if method == "afps_npdu" else (1, None)
-            reqs.append(Request(i, f.points.shape[0], f.c, m, k, 0, float(arr[i]), pinned[i % pool]))
-        s = Scheduler(ex, budget, max_inflight=8, max_batch=32)
-        done = s.run(reqs)
-        torch.cuda.synchronize()
-        out = latency_summary(done)
-        out.update({"offered_fps": lam, "peak_waiting": s.peak_waiting, "peak_arena_bytes": s.peak_bytes})
-        return out
-
-    for method, count in (("afps_npdu", frames_npdu), ("plain_fps", frames_fps)):
-        stream(method, 6, 1000.0)            # warm-up (plans, kernel attributes)
-        res[method] = {}
-        for lam in rates:
-            r = stream(method, count, float(lam))
-            res[method][str(lam)] = r
-            log("serve %s @%d/s: p50 %.2f ms p99 %.2f ms, %.3e pts/s, peak queue %d" %
-                (method, lam, r["p50_ms"], r["p99_ms"], r["sampled_pts_per_s"] or 0, r["peak_waiting"]))
-    return res
-
-
-def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` (the NPDU step) from the committed
-    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel sources changed
-    since or that kernel was not profiled."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "pooled_npdu_kernel_batch256_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    src = "".join(open(os.path.join(ROOT, s)).read() for s in rec["sources"])
-    if hashlib.sha256(src.encode()).hexdigest() != rec["source_sha256"]:
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    return k["traffic_bytes_per_launch"] if k else None
-
-
 def shader_clock_mhz():
     """The driver's current shader-clock level (sysfs pp_dpm_sclk, the line
     marked '*'), in MHz, for every GPU that exposes it; None where unreadable."""
@@ -388,18 +359,121 @@ def host_cpu_model():
     return None
 
 
+
+
+def serving(torch, ops_fn, rates=(50, 200, 800), seconds=10.0, max_frames=2000, pool=48, seed=1):
+    """Open-loop Poisson streams of LiDAR frames (N uniform in [16384, 131072],
+    C = N/8, M in {8, 16, 32}, k = 64) through the continuous-batching server:
+    AFPS-NPDU for min(2000 frames, 10 s of arrivals) per rate, plain FPS for a
+    fixed 10 s window per rate (what completed, and the queue left at the
+    end).  Per-frame latency from arrival to completion, the indices back on
+    the host.  The served launches' roofline: algorithmic ops of each batch
+    (from its picks) over its launches' HIP-event time."""
+    from paper_2208_08795_amd import synth
+    from paper_2208_08795_amd.serve import GpuExecutor, Request, Scheduler, latency_summary
+    rng = np.random.default_rng(seed)
+    log("generating %d serving frames" % pool)
+    frames = synth.frame_stream(rate=1.0, count=pool, seed=seed)
+    pinned = [torch.from_numpy(f.points).pin_memory() for f in frames]
+    budget = 256 << 20
+    ex = GpuExecutor(budget, streams=4, keep_results=True, timing=True)
+    res = {"budget_bytes": budget,
+           "frames": "pool of %d distinct synthetic 64-beam frames, N uniform in [16384, 131072], C = N/8, "
+                     "M in {8,16,32}, k = 64; indices copied back to pinned host memory per frame" % pool,
+           "length": "AFPS-NPDU: min(%d frames, %.0f s of arrivals) per rate; plain FPS: a %.0f s window per rate"
+                     % (max_frames, seconds, seconds)}
+
+    def stream(method, count, lam, window=None):
+        gaps = rng.exponential(1.0 / lam, count)
+        arr = np.cumsum(gaps) - gaps[0]
+        reqs = []
+        for i in range(count):
+            f = frames[i % pool]
+            m, k = (f.m, f.k) if method == "afps_npdu" else (1, None)
+            reqs.append(Request(i, f.points.shape[0], f.c, m, k, 0, float(arr[i]), pinned[i % pool]))
+        s = Scheduler(ex, budget, max_inflight=8, max_batch=32)
+        done = s.run(reqs, window=window)
+        torch.cuda.synchronize()
+        out = latency_summary(done)
+        out.update({"offered_fps": lam, "offered_frames": count, "peak_waiting": s.peak_waiting,
+                    "peak_arena_bytes": s.peak_bytes})
+        if window is not None:
+            out.update({"window_s": window, "left_waiting": s.left_waiting,
+                        "oldest_wait_ms": s.oldest_wait_s * 1e3})
+        ops = ms = 0.0
+        per_launch = []
+        for b in s.batch_log:
+            if b.kernel_ms is None or b.kernel_ms <= 0:
+                continue
+            o = sum(ops_fn(r) for r in b.requests if r.state == "done")
+            ops += o
+            ms += b.kernel_ms
+            per_launch.append(o / (b.kernel_ms * 1e-3) / 1e12)
+        if per_launch:
+            out["roofline"] = {"bound": "alu", "unit": "TOPS (fp32 VALU lane-ops)", "peak": VALU_PEAK_TOPS,
+                               "achieved_mean_per_launch": float(np.mean(per_launch)),
+                               "frac": float(np.mean(per_launch)) / VALU_PEAK_TOPS,
+                               "launches": len(per_launch), "mean_launch_ms": ms / len(per_launch),
+                               "what": "per batch: its algorithmic ops over its sampling launches' HIP-event "
+                                       "time (batches on four streams overlap), mean over batches"}
+        return out
+
+    for method in ("afps_npdu", "plain_fps"):
+        stream(method, 6, 1000.0)            # warm-up (plans, kernel attributes)
+        res[method] = {}
+        for lam in rates:
+            if method == "afps_npdu":
+                r = stream(method, int(min(max_frames, math.ceil(seconds * lam))), float(lam))
+            else:
+                r = stream(method, int(math.ceil(seconds * lam)), float(lam), window=seconds)
+            res[method][str(lam)] = r
+            log("serve %s @%d/s: %d frames, p50 %.2f ms p99 %.2f ms, %.3e pts/s, left waiting %s" %
+                (method, lam, r.get("frames", 0), r.get("p50_ms") or 0, r.get("p99_ms") or 0,
+                 r.get("sampled_pts_per_s") or 0, r.get("left_waiting", 0)))
+    return res
+
+
+def served_ops(req):
+    """Algorithmic ops of one served frame from its picks (NPDU: 9 per window
+    update + the argmax compares; plain FPS: 10 per point per iteration)."""
+    if req.result is None:
+        return 0.0
+    out = req.result.numpy()
+    if req.k is None and req.m == 1:
+        return 10.0 * (req.c - 1) * req.n
+    return float(npdu_counts([req.n], [req.c], out, [0], req.m, req.k)["ops"])
+
+
+
+
+def lscpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return host_cpu_model()
+
+
 def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
-    """The oracle (never tuned) on the host cores: one cloud per task."""
+    """The oracle (never tuned) on the host: single-thread latency per cloud,
+    and throughput with one cloud per task on every host core the process may
+    use, capped at the 16 threads a one-GPU machine grants a job.  Median of up to
+    five whole passes over a bounded sample, input generation untimed."""
     import oracle
     oracle.load()
-    cores = min(16, os.cpu_count() or 1)
+    nproc = os.cpu_count() or 1
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
+    threads = max(1, min(16, allowed))
     # bounded sample: clouds in order until the estimated single-core work
-    # (~ N^2 / (8 m) compare steps) reaches the budget
+    # (~ N C / m x 2 ns) reaches the budget
     est, take = 0.0, 0
     for p, c in zip(clouds, cs):
         est += len(p) * c / m * 2e-9
         take += 1
-        if est > budget_s * cores * 0.5:
+        if est > budget_s * threads * 0.5:
             break
     idx = list(range(take))
 
@@ -407,27 +481,33 @@ def cpu_baseline(clouds, cs, m, k, gpu_out, offsets, budget_s=20.0):
         t = time.perf_counter()
         o = oracle.afps(clouds[i], cs[i], m, k, 0)
         return o, time.perf_counter() - t
-    # whole passes over the sample, the median reported, within the time budget
+
+    # latency leg: one thread, every cloud of the sample once (the first 64 at most)
+    lat_idx = idx[:64]
+    lat = [one(i)[1] * 1e3 for i in lat_idx]
+    # throughput leg: whole passes on `threads` threads
     dts = []
-    with cf.ThreadPoolExecutor(cores) as ex:
+    with cf.ThreadPoolExecutor(threads) as ex:
         while len(dts) < 5 and sum(dts) < budget_s:
             t0 = time.perf_counter()
             res = list(ex.map(one, idx))
             dts.append(time.perf_counter() - t0)
     dt = float(np.median(dts))
     outs = [o for o, _ in res]
-    per_cloud_ms = [1e3 * t for _, t in res]   # each cloud runs on one thread: its latency
     same = all(np.array_equal(outs[j], gpu_out[offsets[i]:offsets[i] + cs[i]]) for j, i in enumerate(idx))
     samples = sum(cs[i] for i in idx)
-    return {"value": samples / dt, "unit": "sampled pts/s", "cores": cores, "kind": "oracle",
+    return {"value": samples / dt, "unit": "sampled pts/s", "cores": threads, "kind": "oracle",
             "sample": "first %d of the 256 clouds (%d points, %d samples), AFPS M=%d NPDU k=%d, one cloud "
-                      "per thread; median of %d passes, %.2f s each" %
-                      (take, sum(len(clouds[i]) for i in idx), samples, m, k, len(dts), dt),
-            "host_cpu": host_cpu_model(),
+                      "per task on %d threads; median of %d passes, %.2f s each" %
+                      (take, sum(len(clouds[i]) for i in idx), samples, m, k, threads, len(dts), dt),
+            "host": {"nproc": nproc, "affinity_cpus": allowed, "threads_used": threads,
+                     "thread_cap": "16 threads: a one-GPU box's share of host CPUs",
+                     "cpu_model": lscpu_model()},
             "matches_gpu": bool(same),
-            "single_thread_ms_per_cloud": {"p50": float(np.percentile(per_cloud_ms, 50)),
-                                           "max": float(np.max(per_cloud_ms)),
-                                           "mean_points": float(np.mean([len(clouds[i]) for i in idx]))}}
+            "single_thread_latency_ms_per_cloud": {"p50": float(np.percentile(lat, 50)),
+                                                    "p99": float(np.percentile(lat, 99)),
+                                                    "clouds": len(lat),
+                                                    "mean_points": float(np.mean([len(clouds[i]) for i in lat_idx]))}}
 
 
 def main():
@@ -436,29 +516,30 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--streams", type=int, default=2,
-                    help="streams the timed steps alternate over (each with its own plan and output)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-single", action="store_true", help="skip single-cloud latencies")
+    ap.add_argument("--no-single", action="store_true", help="skip single-cloud latencies and sweeps")
     ap.add_argument("--no-fps", action="store_true", help="skip the plain-FPS comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving streams")
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (built-in variant rule)")
-    ap.add_argument("--occupancy", type=float, default=None,
-                    help="plan wave budget in waves per SIMD for the timed batch (skips its tuning; "
-                         "0 = the built-in rule, >= 1.5 = two pooled waves per SIMD)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuners (built-in rules)")
+    ap.add_argument("--pool", type=str, default=None,
+                    help="pooled launch shape 'waves,groups' for the timed batch (skips its tuning)")
+    ap.add_argument("--l2-up-to", type=int, default=None,
+                    help="NPDU sectors of at most this many points read coordinates from L2 (with --pool)")
+    ap.add_argument("--only-timed", action="store_true",
+                    help="stop after the timed launch (for profiler runs: warm-up and timed launches only)")
     args = ap.parse_args()
-    if args.streams < 1:
-        ap.error("--streams must be at least 1")
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent clouds would shard by request with no exchange)", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.steps > 4096 or args.warmup < 0:
+        ap.error("--steps must be in [1, 4096] (rounds of one launch) and --warmup >= 0")
 
     import torch
-    from paper_2208_08795_amd import binding, synth
+    from paper_2208_08795_amd import autotune, binding, synth
     from paper_2208_08795_amd.quality import coverage_radius
 
-    binding.lib()
+    L = binding.lib()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     M, K = 8, 32
@@ -467,6 +548,7 @@ def main():
     sizes = [len(p) for p in clouds]
     cs = [n // 4 for n in sizes]
     xyz_all = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    xyz_copy = xyz_all.clone()                  # the rounds alternate over two resident inputs
     total_samples = sum(cs)
 
     # A plain device copy of known size: rocprofv3 --pmc runs read its
@@ -475,70 +557,138 @@ def main():
     calib2 = torch.empty_like(calib)
     calib2.copy_(calib)
 
-    tuned_occ = args.occupancy is None and not args.no_tune
-    if args.occupancy is not None:
-        binding.set_plan_occupancy(args.occupancy)
-    elif tuned_occ:
-        from paper_2208_08795_amd import autotune
-        log("autotuning the batch plan's wave budget")
-        occ = autotune.tune_occupancy(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256,
-                                      streams=args.streams, log=log)
-        res_occ = [[f, round(t, 4)] for f, t in occ]
-    S = args.streams
-    streams = [stream] + [torch.cuda.Stream(device=dev) for _ in range(S - 1)]
-    plans = [binding.BatchPlan(sizes, cs, [M] * 256, [K] * 256, [0] * 256, device=dev) for _ in range(S)]
-    outs = [torch.empty(plans[0].total_samples, dtype=torch.int32, device=dev) for _ in range(S)]
-    plan, out = plans[0], outs[0]
-    log("AFPS-NPDU plan: %d items, %d launch(es), %d stream(s)" % (plan.items, plan.launches, S))
-    wall, warm = time_steps(torch, plans, xyz_all, outs, args.steps, args.warmup, streams)
-    sclk = shader_clock_mhz()
-    ms_per_step = wall * 1e3 / args.steps
-    value = total_samples / (wall / args.steps)
-    out_np = out.cpu().numpy()
-    log("AFPS-NPDU: %.3f ms/step, %.3e sampled pts/s" % (ms_per_step, value))
-    ev_ms = step_latency(torch, plan, xyz_all, out, max(20, args.steps), stream)
+    res_tune = None
+    if args.pool is not None:
+        w, g = (int(x) for x in args.pool.split(","))
+        binding.set_pool_policy(w, g, True, 3)
+        if args.l2_up_to:
+            binding.tune_npdu(args.l2_up_to, K, False)
+    elif not args.no_tune:
+        log("tuning the pooled NPDU launch on the batch")
+        res_tune = autotune.tune_npdu(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256, rounds=20, log=log)
+    plan = binding.BatchPlan(sizes, cs, [M] * 256, [K] * 256, [0] * 256, device=dev)
+    label = "pooled_npdu_kernel<%d>" % plan.pool_waves
+    if plan.pool_groups > 1:
+        label += " x%d per CU" % plan.pool_groups
+    l2_up_to = max((n for n in range(64, 8193, 64) if not binding.npdu_xyz_in_lds(n, K)), default=0)
+    log("AFPS-NPDU plan: %d sectors, %s, coordinates in L2 up to %d points" % (plan.items, label, l2_up_to))
 
-    res = {"metric": METRIC, "value": value, "unit": "sampled pts/s", "n_gpus": 1, "steps": args.steps,
+    # reference: one eager pass (checked against the oracle by cpu_baseline)
+    ref = plan.launch(xyz_all, stream=stream)
+    torch.cuda.synchronize()
+    out_np = ref.cpu().numpy()
+
+    # ---- the timed steps: one launch of K rounds, each round its own output
+    steps, warm = args.steps, args.warmup
+    outs = torch.full((steps, plan.total_samples), -7, dtype=torch.int32, device=dev)
+    inputs = (xyz_all, xyz_copy)
+    table = plan.round_table([(inputs[r % 2], outs[r]) for r in range(steps)])
+    if warm:
+        wtable = plan.round_table([(inputs[r % 2], outs[r % steps]) for r in range(warm)])
+        plan.launch_rounds(wtable, stream=stream)
+    torch.cuda.synchronize()
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev_a.record(stream)
+    plan.launch_rounds(table, stream=stream)
+    ev_b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = ev_a.elapsed_time(ev_b)
+    sclk = shader_clock_mhz()
+    plan.status(stream=stream)
+    if not bool((outs == ref.unsqueeze(0)).all()):
+        raise SystemExit("bench: a round's indices differ from the single pass")
+    ms_per_step = wall * 1e3 / steps
+    value = total_samples * steps / wall
+    log("AFPS-NPDU: %d rounds in one launch, %.4f ms/step (launch %.3f ms), %.3e sampled pts/s" %
+        (steps, ms_per_step, launch_ms, value))
+
+    res = {"metric": METRIC, "value": value, "unit": "sampled pts/s", "n_gpus": 1, "steps": steps,
            "warmup": warm, "ms_per_step": ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "256 object-like clouds, N log-uniform [1024, 32768] (%d points), "
-                                  "C = N/4 (%d samples), AFPS M=8 with NPDU k=32, one persistent launch "
-                                  "per step replayed from a hipGraph; consecutive steps alternate over %d "
-                                  "streams, each with its own plan workspace and output"
-                                  % (sum(sizes), total_samples, S),
+                                  "C = N/4 (%d samples), AFPS M=8 with NPDU k=32; the K timed steps are one "
+                                  "pooled launch of K rounds of the batch (alternating two resident inputs, "
+                                  "one output per round)" % (sum(sizes), total_samples),
                       "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples,
-                      "streams": S}}
-    if tuned_occ:
-        res["plan_occupancy_tuning"] = {"waves_per_simd_vs_ms": res_occ, "chosen": res_occ[0][0],
-                                        "what": "ms per step, timed as the steps are (%d stream(s))" % S}
-    elif args.occupancy is not None:
-        res["plan_occupancy"] = args.occupancy
+                      "pool_launch": label, "coordinates_in_l2_up_to_points": l2_up_to}}
+    if res_tune is not None:
+        res["npdu_tuning"] = {"best": {"shape": list(res_tune["best"][0]), "l2_up_to": res_tune["best"][1],
+                                       "seed_sleep": res_tune["best"][2][0], "seed_priority": res_tune["best"][2][1],
+                                       "ms_per_step": round(res_tune["best"][3], 4)},
+                              "rows": [[list(r[0]), r[1], list(r[2]), round(r[3], 4)] for r in res_tune["rows"]],
+                              "seconds": round(res_tune["seconds"], 2),
+                              "what": "ms per batch in one launch of 20 rounds, per pooled launch shape "
+                                      "(waves, workgroups per CU), L2 placement bound and seeding (sleep, priority)"}
     res["sclk_mhz_after_timed_steps"] = sclk
-    res["batch_latency"] = {"unit": "ms", "what": "one step alone (whole batch of 256 clouds, graph launches "
-                                                  "one at a time on one stream), HIP events",
+
+    # ---- roofline of the dominant kernel, on the timed launch's own time
+    cnt = npdu_counts(sizes, cs, out_np, plan.offsets, M, K)
+    stamps = None
+    wall_khz = int(L.afps_wall_clock_khz())
+    if not args.only_timed:
+        _, stamps = plan.launch_stamped(xyz_all, stream=stream)
+        torch.cuda.synchronize()
+    cyc = stamp_cycles(stamps, wall_khz) if stamps is not None else None
+    clock_ghz = (cyc or {}).get("sclk_ghz") or PEAK_CLOCK_GHZ
+    launch_s = launch_ms / 1e3
+    round_s = launch_s / steps
+    ops_launch = cnt["ops"] * steps
+    hbm_round = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
+    lds_round = 20 * cnt["updates"]              # 16 B read (x, y, z, D) + 4 B written per update
+    lds_peak_tbs = CUS * LDS_BYTES_PER_CLK_PER_CU * clock_ghz * 1e9 / 1e12
+    rec = counter_record(label)
+    roof = {"bound": "alu", "kernel": label, "achieved": ops_launch / launch_s / 1e12, "peak": VALU_PEAK_TOPS,
+            "unit": "TOPS (fp32 VALU lane-ops)", "frac": ops_launch / launch_s / 1e12 / VALU_PEAK_TOPS,
+            "traffic": (int(rec["traffic_bytes_per_round"] * steps) if rec and rec.get("traffic_bytes_per_round")
+                        else None),
+            "time_basis": "the timed launch of %d rounds (the K steps), HIP events on its stream; `value` "
+                          "divides the same launch's samples by its synchronised wall time" % steps,
+            "avg_launch_ms": launch_ms, "rounds_per_launch": steps, "launches_timed": 1,
+            "algorithmic_ops_per_launch": ops_launch,
+            "ops_count": "9 per window distance update (3 sub, 3 mul, 2 add, 1 min) + (k+1) window compares + "
+                         "ceil(n_s/64) block-maximum compares per iteration",
+            "alg1_scan_ops_per_launch": cnt["alg1_scan_ops"] * steps,
+            "alg1_scan_frac": cnt["alg1_scan_ops"] * steps / launch_s / 1e12 / VALU_PEAK_TOPS,
+            "distance_updates_per_launch": cnt["updates"] * steps, "iterations_per_round": cnt["iterations"],
+            "hbm_bytes_per_launch": hbm_round * steps, "hbm_frac": hbm_round / round_s / 1e9 / HBM_PEAK_GBS,
+            "lds": {"algorithmic_bytes_per_launch": lds_round * steps,
+                    "achieved_tbs": lds_round / round_s / 1e12, "peak_tbs": lds_peak_tbs,
+                    "frac": lds_round / round_s / 1e12 / lds_peak_tbs,
+                    "peak_basis": "%d CUs x %.0f B/clk (measured, 128-bit reads) x %.3f GHz (measured)" %
+                                  (CUS, LDS_BYTES_PER_CLK_PER_CU, clock_ghz)},
+            "clock_ghz": clock_ghz}
+    if rec:
+        valu = rec["SQ_INSTS_VALU_per_round"]
+        roof["valu_issue_frac"] = valu * VALU_CYCLES_PER_INST / (CUS * SIMDS_PER_CU * round_s * clock_ghz * 1e9)
+        kb = rec["SQ_INSTS_LDS_per_round"] * LDS_BYTES_PER_INST
+        roof["lds"].update({"kernel_bytes_per_launch": kb * steps, "kernel_frac": kb / round_s / 1e12 / lds_peak_tbs})
+        roof["counters_per_round"] = {k: v for k, v in rec.items() if k.endswith("_per_round")}
+        roof["counters_note"] = ("SQ and traffic counters per round from the committed rocprofv3 record of this "
+                                 "launch layout (kernel sources unchanged since); VALU issue = SQ_INSTS_VALU x "
+                                 "%d cycles over %d SIMDs x the round's cycles" % (VALU_CYCLES_PER_INST,
+                                                                                 CUS * SIMDS_PER_CU))
+    else:
+        roof["valu_issue_frac"] = None
+        roof["counters_note"] = "no rocprofv3 counter record matches the current kernel sources and layout"
+    res["roofline"] = roof
+    if cyc is not None:
+        res["cycles_per_iteration_device"] = cyc
+    if args.only_timed:
+        print(json.dumps(res), flush=True)
+        return
+
+    # ---- one step's own latency (one pass at a time, graph replays)
+    plan.launch(xyz_all, out_all=ref, graph=True, stream=stream)
+    torch.cuda.synchronize()
+    ev_ms = _event_ms(torch, lambda: plan.launch(xyz_all, out_all=ref, graph=True, stream=stream), stream,
+                      max(20, min(steps, 100)))
+    res["batch_latency"] = {"unit": "ms", "what": "one step alone (the whole batch of 256 clouds, one pooled "
+                                                  "launch per step, graph replays one at a time), HIP events",
                             "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
 
-    # Roofline of the dominant kernel (the pooled NPDU kernel is the step).
-    pool_label = "pooled_npdu_kernel<%d>" % plan.pool_waves
-    if plan.pool_groups > 1:
-        pool_label += " x%d per CU" % plan.pool_groups
-    ops, upd = npdu_work(sizes, cs, out_np, plan.offsets, M, K)
-    kern_ms = time_kernel(torch, plan, xyz_all, out, max(10, args.steps), stream)
-    kern_s = float(np.mean(kern_ms)) / 1e3
-    hbm_bytes = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
-    res["roofline"] = {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": VALU_PEAK_TOPS,
-                       "unit": "TOPS (fp32 VALU ops)", "frac": ops / kern_s / 1e12 / VALU_PEAK_TOPS,
-                       "traffic": counter_traffic(pool_label),
-                       "kernel": pool_label,
-                       "algorithmic_ops_per_launch": ops, "distance_updates_per_launch": upd,
-                       "hbm_bytes_per_launch": hbm_bytes,
-                       "hbm_frac": hbm_bytes / kern_s / 1e9 / HBM_PEAK_GBS,
-                       "avg_launch_ms": kern_s * 1e3,
-                       "avg_launch_what": "queue reset + pooled kernel, eager launches, HIP events on the "
-                                          "launch stream (the step's graph replay adds its launch overhead)"}
-
     if not args.no_tune:
-        from paper_2208_08795_amd import autotune
         log("autotuning full-update variants")
         tab = autotune.tune(log=log)
         res["autotune"] = {k: [[int(n), int(w), int(p), round(ms, 4)] for n, w, p, ms in v]
@@ -546,31 +696,41 @@ def main():
         res["autotune"]["seconds"] = round(tab["seconds"], 2)
 
     if not args.no_fps:
-        binding.set_plan_occupancy(0.0)      # plain FPS: grids as large as fit
-        fplans = [binding.BatchPlan(sizes, cs, [1] * 256, [None] * 256, [0] * 256, device=dev) for _ in range(S)]
-        fouts = [torch.empty(fplans[0].total_samples, dtype=torch.int32, device=dev) for _ in range(S)]
-        fplan, fout = fplans[0], fouts[0]
-        fsteps = max(3, args.steps // 4)
-        fwall, _ = time_steps(torch, fplans, xyz_all, fouts, fsteps, 1, streams)
-        fvalue = total_samples / (fwall / fsteps)
+        fplan = binding.BatchPlan(sizes, cs, [1] * 256, [None] * 256, [0] * 256, device=dev)
+        fout = fplan.launch(xyz_all, stream=stream, graph=True)
+        torch.cuda.synchronize()
+        fsteps = max(3, min(steps // 10, 20))
+        fev = _event_ms(torch, lambda: fplan.launch(xyz_all, out_all=fout, graph=True, stream=stream), stream,
+                        fsteps)
+        fms = float(np.mean(fev))
+        fops, fupd = fps_ops(sizes, cs)
+        fvalue = total_samples / (fms / 1e3)
         fout_np = fout.cpu().numpy()
-        fev = step_latency(torch, fplan, xyz_all, fout, 3, stream)
-        log("plain FPS: %.3f ms/step, %.3e sampled pts/s" % (fwall * 1e3 / fsteps, fvalue))
-        res["plain_fps"] = {"value": fvalue, "unit": "sampled pts/s", "ms_per_step": fwall * 1e3 / fsteps,
-                            "steps": fsteps, "launches": fplan.launches, "streams": S,
+        log("plain FPS: %.3f ms/step, %.3e sampled pts/s" % (fms, fvalue))
+        fhbm = 12 * sum(sizes) + 4 * total_samples + 40 * fplan.items
+        res["plain_fps"] = {"value": fvalue, "unit": "sampled pts/s", "ms_per_step": fms, "steps": fsteps,
+                            "launches": fplan.launches,
                             "latency_p50_ms": percentile(fev, 50), "latency_p99_ms": percentile(fev, 99),
-                            "afps_npdu_speedup": value / fvalue}
-        # quality: coverage radius against plain FPS (fp64, 32 clouds)
+                            "afps_npdu_speedup": value / fvalue,
+                            "roofline": {"bound": "alu", "achieved": fops / (fms / 1e3) / 1e12,
+                                         "peak": VALU_PEAK_TOPS, "unit": "TOPS (fp32 VALU lane-ops)",
+                                         "frac": fops / (fms / 1e3) / 1e12 / VALU_PEAK_TOPS,
+                                         "algorithmic_ops_per_launch": fops, "distance_updates_per_launch": fupd,
+                                         "hbm_bytes_per_launch": fhbm,
+                                         "hbm_frac": fhbm / (fms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                         "avg_launch_ms": fms,
+                                         "time_basis": "one step (the plan's persistent launches, one workgroup "
+                                                       "per cloud), HIP events, steps one at a time",
+                                         "ops_count": "10 per point per iteration (9 for its distance update, 1 "
+                                                      "argmax compare)"}}
         ratios = []
         for i in range(0, 256, 8):
             o = plan.offsets[i]
-            r_n = coverage_radius(clouds[i], out_np[o:o + cs[i]])
-            r_f = coverage_radius(clouds[i], fout_np[o:o + cs[i]])
-            ratios.append(r_n / r_f)
+            ratios.append(coverage_radius(clouds[i], out_np[o:o + cs[i]]) /
+                          coverage_radius(clouds[i], fout_np[o:o + cs[i]]))
         res["coverage_radius_vs_fps"] = {"mean": float(np.mean(ratios)), "max": float(np.max(ratios)),
                                          "clouds": len(ratios)}
-        for p in fplans:
-            p.close()
+        fplan.close()
 
     if not args.no_single:
         single = single_cloud_latency(torch, binding, synth, stream)
@@ -578,24 +738,25 @@ def main():
         iters = {"cube_n2048_c512_fps": 511, "lidar_n32768_c8192_fps": 8191, "lidar_n32768_c8192_npdu_m16_k64": 511,
                  "object_n8192_c2048_afps_m32": 63, "object_n8192_c2048_npdu_m32_k32": 63,
                  "object_n8192_c2048_fps": 2047}
-        res["cycles_per_iteration"] = {k: round(v * 1e-3 * CLOCK_GHZ * 1e9 / iters[k], 1) for k, v in single.items()}
-        res["cycles_per_iteration"]["note"] = "call time x 2.4 GHz / iterations of the longest sector (launch included)"
-        res["object_n8192_c2048_sweep"], res["npdu_readings"] = object_sweep(torch, binding, synth, stream)
+        res["cycles_per_iteration"] = {k: round(v * 1e-3 * clock_ghz * 1e9 / iters[k], 1) for k, v in single.items()}
+        res["cycles_per_iteration"]["note"] = ("call time x the measured shader clock (%.3f GHz) / iterations of the "
+                                               "longest sector (launch included)" % clock_ghz)
+        res["object_n8192_c2048_sweep"], res["npdu_readings"] = object_sweep(torch, binding, synth, stream, clock_ghz)
         res["sortedness"] = sortedness(torch, binding, synth, stream)
         res["grouping_ball_query"] = grouping(torch, binding, synth, stream)
 
     if not args.no_serve:
-        res["serving"] = serving(torch)
+        res["serving"] = serving(torch, served_ops)
         mid = res["serving"]["afps_npdu"]["200"]
-        res["latency"] = {"unit": "ms", "what": "per frame, arrival to completion, AFPS-NPDU serving "
-                                               "at 200 frames/s", "p50": mid["p50_ms"], "p99": mid["p99_ms"]}
+        res["latency"] = {"unit": "ms", "what": "per frame, arrival to completion (indices back on the host), "
+                                               "AFPS-NPDU serving at 200 frames/s", "p50": mid["p50_ms"],
+                          "p99": mid["p99_ms"]}
 
     if not args.no_cpu:
         log("oracle CPU baseline")
         res["cpu_baseline"] = cpu_baseline(clouds, cs, M, K, out_np, plan.offsets)
         log("cpu baseline: %s" % res["cpu_baseline"])
-    for p in plans:
-        p.close()
+    plan.close()
     print(json.dumps(res), flush=True)
 
 

@@ -166,7 +166,7 @@ size_t afps_plan_workspace_bytes(const afps_plan *plan);
 
 /*
  * Workspace bytes of a plan with `items` work items in total (one per sector,
- * i.e. the sum of m over the batch): a 34.75 KB header of queue counters, the
+ * i.e. the sum of m over the batch): a 66.75 KB header of queue counters, the
  * NPDU queue table and the table of each pooled wave's first sector, plus 40
  * bytes per item, rounded up to 256.  Lets a caller reserve device memory before building
  * the plan.  Host-only arithmetic; 0 for items <= 0.
@@ -202,6 +202,32 @@ int afps_plan_launch(const afps_plan *plan, const float *xyz_all, int32_t *out_a
  */
 int afps_plan_graph_launch(afps_plan *plan, const float *xyz_all, int32_t *out_all,
                            void *workspace, void *stream);
+
+/*
+ * Several rounds of the plan's batch in ONE pooled launch: a stream of
+ * batches with the plan's layout (e.g. consecutive steps over fresh inputs),
+ * processed back to back on the device with no kernel boundary between
+ * them.  Round r reads rounds[r].xyz_all and writes rounds[r].out_all (both
+ * laid out as for afps_plan_launch).  Each wave takes the highest-priority
+ * sector that fits its workgroup's free LDS pages from the lowest round with
+ * sectors left, or from the next round when none of that one fits, so the
+ * next batch's sectors start as soon as pages free up.  Every output of every
+ * round is the same as a separate afps_plan_launch of that round gives.
+ *   rounds    DEVICE array of `count` afps_round entries, 1 <= count <= 4096
+ *   workspace DEVICE, >= afps_plan_rounds_workspace_bytes(plan, count), the
+ *             plan's tables uploaded into it (afps_plan_upload); the queue
+ *             counters of every round follow the plan's own workspace
+ * Only for plans whose sectors all use NPDU (AFPS_ERR_UNSUPPORTED otherwise)
+ * and not with input checking on (each round's clouds are unknown to the
+ * host).  Kernel launches only (capturable); asynchronous on `stream`.
+ */
+typedef struct afps_round {
+    const float *xyz_all;
+    int32_t *out_all;
+} afps_round;
+size_t afps_plan_rounds_workspace_bytes(const afps_plan *plan, int32_t rounds);   /* 0 if invalid */
+int afps_plan_launch_rounds(const afps_plan *plan, const afps_round *rounds, int32_t count,
+                            void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Status of the plan's last launch with `workspace`: waits for `stream`, then
@@ -313,14 +339,18 @@ void afps_tune_reset(void);   /* forgets every tuned entry and the pool policy (
  */
 int afps_tune_npdu(int32_t n_s_max, int32_t k_max, int32_t xyz_in_lds);
 int afps_npdu_xyz_in_lds(int32_t n_s, int32_t k);
+/* Forget the NPDU placement entries and the pool policy (afps_set_pool_policy);
+ * the full-update tuning and the occupancy budget stay. */
+void afps_tune_npdu_clear(void);
 
 /*
  * Policy of the pooled NPDU launch of batch plans created afterwards:
- *   waves, groups_per_cu  the launch shape: 4 or 8 waves per workgroup and 1
- *                         or 2 workgroups per CU, each owning that share of
- *                         the CU's LDS pages (used when every sector fits the
- *                         share); 0, 0 = chosen from the plan's occupancy
- *                         budget and its sectors (afps_set_plan_occupancy)
+ *   waves, groups_per_cu  the launch shape: one workgroup per CU of 4, 8, 12
+ *                         or 16 waves (one to four per SIMD) owning all of
+ *                         the CU's LDS pages, or two of 4 waves owning half
+ *                         each (used when every sector fits half); 0, 0 =
+ *                         chosen from the plan's occupancy budget and its
+ *                         sectors (afps_set_plan_occupancy)
  *   seed_sleep            1 = first sectors with slack before the plan's
  *                         longest one wait a sleep period before loading
  *   seed_priority         issue priority 0..3 of the wave running its

@@ -11,9 +11,14 @@ table:
 * ``batch`` (throughput): many sectors of the class in one launch, as inside
   a batch plan; here the variant that keeps the SIMDs busiest wins.
 
-The NPDU kernels are not tuned: they run one wave per sector by design and
-their variant follows from the sector size.  Results can be written to a
-cache file that the library reads at first use (AFPS_TUNE_CACHE).
+For the pooled NPDU launch of batch plans (one wave per sector, sectors
+placed into each CU's LDS pages), ``tune_npdu`` times the caller's own batch
+as it runs (one launch of several rounds) under each launch shape (waves per
+workgroup and workgroups per CU: the sector-to-CU mapping), each placement of
+the sectors' coordinates (LDS records, or L2 for the smaller sectors, which
+take a quarter of the pages) and each seeding policy, and installs the
+fastest.  Results can be written to a cache file that the library reads at
+first use (AFPS_TUNE_CACHE).
 """
 from __future__ import annotations
 
@@ -136,3 +141,85 @@ def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.0, 1.0, 2.0, 4
     res.sort(key=lambda x: x[1])
     binding.set_plan_occupancy(res[0][0] if install else 0.0)
     return res
+
+
+# Pooled launch shapes (waves per workgroup, workgroups per CU) and coordinate
+# placements (sectors of at most n points read their coordinates from L2; 0 =
+# every sector keeps them in LDS) that tune_npdu tries.
+POOL_SHAPES = ((4, 1), (8, 1), (4, 2), (12, 1), (16, 1))
+L2_UP_TO = (0, 1024, 2048, 8192)
+SEEDING = ((True, 3), (False, 3), (True, 0), (False, 0))
+
+
+def _apply_npdu(shape, l2_up_to, seeding, k_max):
+    from . import binding
+    binding.tune_npdu_clear()
+    binding.set_pool_policy(shape[0], shape[1], seeding[0], seeding[1])
+    if l2_up_to:
+        binding.tune_npdu(l2_up_to, k_max, False)
+
+
+def tune_npdu(xyz_all, sizes, cs, ms, ks, starts, rounds: int = 20, reps: int = 3, install: bool = True,
+              cache_path: str | None = None, log=None):
+    """Tune the pooled NPDU launch on the caller's batch: time one launch of
+    `rounds` rounds (median of reps, HIP events) for every launch shape x
+    coordinate placement, then every seeding policy at the best of those; keep
+    the fastest (installed in the library, optionally written to cache_path
+    as "pool" and "npdu" lines).  Outputs of every configuration are checked
+    equal to the first one's.  Returns {"rows": [(shape, l2_up_to, seeding,
+    ms per round)], "best": (...), "seconds": s}."""
+    import torch
+
+    from . import binding
+    t0 = time.perf_counter()
+    dev = xyz_all.device
+    k_max = max(k for k in ks if k is not None)
+    rows, ref = [], None
+
+    def measure(shape, l2, seeding):
+        nonlocal ref
+        _apply_npdu(shape, l2, seeding, k_max)
+        plan = binding.BatchPlan(sizes, cs, ms, ks, starts, device=dev)
+        if (plan.pool_waves, plan.pool_groups) != shape:   # the shape does not fit these sectors
+            plan.close()
+            return None
+        outs = [torch.empty(plan.total_samples, dtype=torch.int32, device=dev) for _ in range(2)]
+        table = plan.round_table([(xyz_all, outs[r % 2]) for r in range(rounds)])
+        plan.launch_rounds(table)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            plan.launch_rounds(table)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b) / rounds)
+        if ref is None:
+            ref = outs[0].clone()
+        if not (torch.equal(outs[0], ref) and torch.equal(outs[1], ref)):
+            raise RuntimeError("tuned NPDU configuration %s/%s/%s changed the indices" % (shape, l2, seeding))
+        plan.close()
+        ms_ = float(np.median(ts))
+        rows.append((shape, l2, seeding, ms_))
+        if log:
+            log("npdu tune: shape %s, L2 up to %d points, seeding %s: %.4f ms per batch" % (shape, l2, seeding, ms_))
+        return ms_
+
+    for shape in POOL_SHAPES:
+        for l2 in L2_UP_TO:
+            measure(shape, l2, SEEDING[0])
+    best = min(rows, key=lambda r: r[3])
+    for seeding in SEEDING[1:]:
+        measure(best[0], best[1], seeding)
+    best = min(rows, key=lambda r: r[3])
+    if install:
+        _apply_npdu(best[0], best[1], best[2], k_max)
+    else:
+        binding.tune_npdu_clear()
+    if cache_path:
+        with open(cache_path, "a") as f:
+            f.write("pool %d %d %d %d\n" % (best[0][0], best[0][1], int(best[2][0]), best[2][1]))
+            if best[1]:
+                f.write("npdu %d %d 0\n" % (best[1], k_max))
+    return {"rows": rows, "best": best, "seconds": time.perf_counter() - t0}

@@ -70,7 +70,10 @@ def lib():
             "afps_init": ([], ctypes.c_int),
             "afps_wall_clock_khz": ([], i32),
             "afps_tune_npdu": ([i32, i32, i32], ctypes.c_int),
+            "afps_plan_rounds_workspace_bytes": ([vp, i32], sz),
+            "afps_plan_launch_rounds": ([vp, vp, i32, vp, sz, vp], ctypes.c_int),
             "afps_npdu_xyz_in_lds": ([i32, i32], ctypes.c_int),
+            "afps_tune_npdu_clear": ([], None),
             "afps_set_pool_policy": ([i32, i32, i32, i32], ctypes.c_int),
             "afps_noalloc_max_items": ([], i32),
             "afps_plan_items": ([vp], i32),
@@ -278,6 +281,40 @@ class BatchPlan:
                                               _stream_handle(stream)))
         return out_all, stamps
 
+    def round_table(self, rounds):
+        """DEVICE table (int64 pairs) of the rounds' (xyz_all, out_all) for
+        launch_rounds; the caller keeps the tensors alive while it is in use."""
+        torch = _torch()
+        rows = []
+        for xyz_all, out_all in rounds:
+            _check_points(xyz_all)
+            if xyz_all.shape[0] < self.total_points:
+                raise ValueError("a round's xyz_all holds fewer points than the plan's clouds")
+            _out(xyz_all, self.total_samples, out_all)
+            rows.append([xyz_all.data_ptr(), out_all.data_ptr()])
+        return torch.tensor(rows, dtype=torch.int64).to(self.workspace.device)
+
+    def launch_rounds(self, rounds, stream=None):
+        """Run the batch once per round in one pooled launch
+        (afps_plan_launch_rounds): `rounds` is a list of (xyz_all, out_all)
+        pairs or a table from round_table()."""
+        torch = _torch()
+        table = rounds if isinstance(rounds, torch.Tensor) else self.round_table(rounds)
+        count = int(table.shape[0])
+        need = int(lib().afps_plan_rounds_workspace_bytes(self._plan, count))
+        if need == 0:
+            raise AfpsError(-2, "round count %d outside [1, 4096] or an empty plan" % count)
+        if self.workspace.numel() < need:
+            self.workspace = torch.empty(need, dtype=torch.uint8, device=self.workspace.device)
+            self._uploaded = False
+        if not self._uploaded:
+            self.upload(stream)
+        _used_on(stream, self.workspace, table)
+        _check(lib().afps_plan_launch_rounds(self._plan, ctypes.c_void_p(table.data_ptr()), count,
+                                             ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                             _stream_handle(stream)))
+        return table
+
     def status(self, stream=None):
         """Raise AfpsError (AFPS_ERR_DEVICE) if a wave of the last launch gave
         up a bounded wait; waits for the stream."""
@@ -466,6 +503,11 @@ def tune_npdu(n_s_max: int, k_max: int, xyz_in_lds: bool):
     """Coordinates of NPDU sectors of at most n_s_max points (windows k <= k_max)
     in LDS or read from L2, for batch plans created afterwards."""
     _check(lib().afps_tune_npdu(n_s_max, k_max, 1 if xyz_in_lds else 0))
+
+
+def tune_npdu_clear():
+    """Forget the NPDU placement and pool policy (full-update tuning stays)."""
+    lib().afps_tune_npdu_clear()
 
 
 def npdu_xyz_in_lds(n_s: int, k: int) -> bool:

@@ -114,7 +114,7 @@ void sort_placement(std::vector<NpduPlacement>& tab) {
 }
 
 bool valid_pool_policy(int waves, int groups, int sleep, int prio) {
-    const bool shape = (waves == 0 && groups == 0) || ((waves == 4 || waves == 8) && (groups == 1 || groups == 2));
+    const bool shape = (waves == 0 && groups == 0) || valid_pool_shape(waves, groups);
     return shape && (sleep == 0 || sleep == 1) && prio >= 0 && prio <= 3;
 }
 
@@ -200,6 +200,7 @@ constexpr size_t kScratchBytes = size_t(1) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 constexpr int kHelperStreams = 4;
+constexpr int kMaxRounds = 4096;   // rounds of one pooled launch (2 MiB of queue counters)
 constexpr int kGridBlocks = 16;
 
 // The barrier blocks of the multi-workgroup plain-FPS kernel and the
@@ -618,8 +619,8 @@ int afps_tune_npdu(int32_t n_s_max, int32_t k_max, int32_t xyz_in_lds) {
 
 int afps_set_pool_policy(int32_t waves, int32_t groups_per_cu, int32_t seed_sleep, int32_t seed_priority) {
     if (!valid_pool_policy(waves, groups_per_cu, seed_sleep, seed_priority))
-        return fail(AFPS_ERR_ARG, "pool shape must be (0, 0) or waves 4|8 and groups 1|2; seed_sleep 0|1; "
-                                  "seed_priority 0..3");
+        return fail(AFPS_ERR_ARG, "pool shape must be (0, 0), (4|8|12|16 waves, 1 group) or (4 waves, 2 groups); "
+                                  "seed_sleep 0|1; seed_priority 0..3");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file_locked();
     g_pool_policy.waves = waves;
@@ -627,6 +628,14 @@ int afps_set_pool_policy(int32_t waves, int32_t groups_per_cu, int32_t seed_slee
     g_pool_policy.seed_sleep = seed_sleep != 0;
     g_pool_policy.seed_priority = seed_priority;
     return AFPS_OK;
+}
+
+void afps_tune_npdu_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
+    const float occupancy = g_pool_policy.waves_per_simd;
+    g_pool_policy = PoolPolicy();
+    g_pool_policy.waves_per_simd = occupancy;
 }
 
 int afps_npdu_xyz_in_lds(int32_t n_s, int32_t k) {
@@ -881,10 +890,21 @@ int check_plan_clouds(const afps_plan* plan, const float* xyz_all, hipStream_t s
     return check_clouds(xyz_all, plan->clouds, stream, names);
 }
 
+// Clear `words` counters on `stream` with a kernel (a memset node would
+// misbehave in a replayed graph).
+int reset_words(unsigned* words, int count, hipStream_t stream) {
+    void* args[] = {&words, &count};
+    AFPS_HIP(hipLaunchKernel(queue_reset_kernel(), dim3((count + 255) / 256), dim3(256), args, 0, stream));
+    return AFPS_OK;
+}
+
 // afps_plan_launch after argument checks: launches only (capturable).
 // `stamps`: per-item timestamps of the pooled NPDU launch, or nullptr.
+// `rounds`/`nrounds`: a launch of several rounds (pooled plans only): per-round
+// inputs and outputs (DEVICE), queue counters after the work items.
 int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
-                     hipStream_t stream, SectorStamp* stamps = nullptr) {
+                     hipStream_t stream, SectorStamp* stamps = nullptr, const PoolRound* rounds = nullptr,
+                     int nrounds = 1) {
     DeviceState* d;
     int rc = device_state(&d);
     if (rc) return rc;
@@ -894,9 +914,11 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
     const PoolSeed* seeds = (const PoolSeed*)((char*)workspace + kPoolSeedOffset);
     const WorkItem* items = (const WorkItem*)((char*)workspace + kItemsOffset);
     int nb = (int)plan->buckets.size();
-    int reset_words = kResetWords;
-    void* rargs[] = {&counters, &reset_words};
-    AFPS_HIP(hipLaunchKernel(queue_reset_kernel(), dim3(1), dim3(kResetWords), rargs, 0, stream));
+    if ((rc = reset_words(counters, kResetWords, stream))) return rc;
+    if (rounds) {
+        qtaken = (unsigned*)((char*)workspace + plan->ws_bytes);
+        if ((rc = reset_words(qtaken, nrounds * kRoundCounters, stream))) return rc;
+    }
 
     auto launch_bucket = [&](int b, hipStream_t s) -> int {
         const PlannedBucket& bk = plan->buckets[b];
@@ -905,6 +927,8 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
             PoolArgs pa{};
             pa.xyz_all = xyz_all;
             pa.out_all = out_all;
+            pa.rounds = rounds;
+            pa.nrounds = nrounds;
             pa.items = items;
             pa.queues = queues;
             pa.qtaken = qtaken;
@@ -1041,6 +1065,32 @@ int afps_plan_launch_stamped(const afps_plan* plan, const float* xyz_all, int32_
     if (((uintptr_t)stamps & 63) != 0) return fail(AFPS_ERR_WORKSPACE, "stamps must be 64-byte aligned");
     if (g_checking && (rc = check_plan_clouds(plan, xyz_all, (hipStream_t)stream))) return rc;
     return plan_launch_impl(plan, xyz_all, out_all, workspace, (hipStream_t)stream, (SectorStamp*)stamps);
+}
+
+size_t afps_plan_rounds_workspace_bytes(const afps_plan* plan, int32_t rounds) {
+    if (!plan || plan->items.empty() || rounds < 1 || rounds > kMaxRounds) return 0;
+    return plan->ws_bytes + round_counters_bytes(rounds);
+}
+
+int afps_plan_launch_rounds(const afps_plan* plan, const afps_round* rounds, int32_t count, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    if (!plan) return fail(AFPS_ERR_NULL, "plan must be non-null");
+    if (plan->items.empty()) return AFPS_OK;
+    if (!rounds) return fail(AFPS_ERR_NULL, "rounds must be non-null");
+    if (count < 1 || count > kMaxRounds)
+        return fail(AFPS_ERR_ARG, "rounds must be in [1, " + std::to_string(kMaxRounds) + "]");
+    if (plan->buckets.size() != 1 || !plan->buckets[0].pool())
+        return fail(AFPS_ERR_UNSUPPORTED, "launches of several rounds take plans whose sectors all use NPDU");
+    const size_t need = afps_plan_rounds_workspace_bytes(plan, count);
+    if (!workspace || workspace_bytes < need)
+        return fail(AFPS_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    if (((uintptr_t)workspace & 255) != 0) return fail(AFPS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (g_checking)
+        return fail(AFPS_ERR_UNSUPPORTED, "input checking cannot read the device round table; "
+                                          "check each round's clouds with afps_check_points");
+    static_assert(sizeof(afps_round) == sizeof(PoolRound), "round table layout");
+    return plan_launch_impl(plan, nullptr, nullptr, workspace, (hipStream_t)stream, nullptr,
+                            (const PoolRound*)rounds, count);
 }
 
 int afps_plan_status(const afps_plan* plan, const void* workspace, void* stream_) {

@@ -56,7 +56,7 @@ constexpr int kMaxNpduLdsXyz = 8192;   // largest sector whose coordinates fit i
 constexpr int kPoolPageBytes = 1024;
 constexpr int kMaxPoolPages = 160;      // pages per workgroup, at most (used-mask of 3 words)
 constexpr int kMaxPoolQueues = 128;     // two per lane in the queue scan
-constexpr int kMaxPoolWaves = 8;
+constexpr int kMaxPoolWaves = 16;
 constexpr int kMaxPoolSeedGroups = 512;
 constexpr int kSeedSleepCycles = 127 * 64;   // one s_sleep(127)
 
@@ -70,13 +70,17 @@ constexpr int npdu_pool_pages(int n, bool xyz_in_lds) {
 // Pages of the sector the built-in placement gives (coordinates in LDS up to 8192 points).
 constexpr int npdu_pool_pages(int n) { return npdu_pool_pages(n, npdu_r_for(n) <= 2); }
 
-// A queue of pooled sectors that all need the same pages, longest first.
+// A queue of pooled sectors that all need the same pages, longest first:
+// items [first, first + count) of the plan, of which the first `seeded` are
+// the first sectors of waves in round 0 (they are not queued in that round).
 struct PoolQueue {
-    int32_t first;     // items [first, first + count) of the plan
+    int32_t first;
     int32_t count;
     int32_t pages;     // pages every item of the queue needs
-    int32_t pad;
+    int32_t seeded;
 };
+// Queue counters of one round of a pooled launch (one per queue).
+constexpr int kRoundCounters = 128;
 static_assert(sizeof(PoolQueue) == 16, "pool queue layout");
 
 // First sector of each pooled wave, assigned when the plan is built: the
@@ -98,7 +102,7 @@ struct CheckSeg {
 
 // Device workspace of a batch plan:
 //   [bucket counters (63) | status word | pool queue counters (128) |
-//    pool queue table (128 x 16 B) | pool seeds (512 x 8 x 8 B) | work items]
+//    pool queue table (128 x 16 B) | pool seeds (512 x 16 x 8 B) | work items]
 constexpr size_t kCounterBytes = 256;
 constexpr int kStatusWord = (int)(kCounterBytes / sizeof(unsigned)) - 1;   // set by a wave that gave up
 constexpr int kMaxBuckets = kStatusWord;
@@ -111,6 +115,11 @@ constexpr int kResetWords = (int)(kPoolTableOffset / sizeof(unsigned));   // cou
 
 constexpr size_t workspace_bytes_for_items(int64_t items) {
     return items <= 0 ? 0 : ((kItemsOffset + (size_t)items * sizeof(WorkItem)) + 255) / 256 * 256;
+}
+// A launch of several rounds adds the queue counters of every round after
+// the work items.
+constexpr size_t round_counters_bytes(int64_t rounds) {
+    return rounds <= 0 ? 0 : ((size_t)rounds * kRoundCounters * sizeof(unsigned) + 255) / 256 * 256;
 }
 
 }  // namespace afps

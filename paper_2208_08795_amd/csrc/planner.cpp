@@ -77,6 +77,10 @@ int32_t largest_sector(int32_t n, int32_t m) { return n / m + (n % m ? 1 : 0); }
 
 int32_t clamp_k(int32_t k, int32_t n_s) { return k > 2 * n_s ? 2 * n_s : k; }
 
+bool valid_pool_shape(int waves, int groups) {
+    return (waves == 4 && (groups == 1 || groups == 2)) || ((waves == 8 || waves == 12 || waves == 16) && groups == 1);
+}
+
 bool npdu_xyz_in_lds(const PoolPolicy& policy, int n, int k) {
     if (npdu_r_for(n) > 2) return false;
     for (const auto& e : policy.placement)
@@ -206,7 +210,7 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
                 bk.cost += st.cost;
                 bk.longest = std::max(bk.longest, st.cost);
             }
-            plan.queues.push_back({first, q.second.second, npdu[q.second.first].pages, 0});
+            plan.queues.push_back({first, q.second.second, npdu[q.second.first].pages, 0});   // seeded below
         }
         bk.count = (int)plan.items.size();
         // Waves per CU: one per SIMD keeps the longest sectors at full speed;
@@ -227,8 +231,7 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
         plan.pool_groups = waves == 8 && max_pages <= plan.pool_pages / 2 ? 2 : 1;
         if (plan.pool_groups == 2) waves = 4;
         if (env.pool.waves > 0 && env.pool.groups > 0) {   // an explicit (tuned) shape
-            const bool ok = (env.pool.waves == 4 || env.pool.waves == 8) &&
-                            (env.pool.groups == 1 || env.pool.groups == 2) &&
+            const bool ok = valid_pool_shape(env.pool.waves, env.pool.groups) &&
                             max_pages <= plan.pool_pages / env.pool.groups;
             if (ok) {
                 waves = env.pool.waves;
@@ -247,7 +250,7 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
         // workgroup's pages), so that a launch starts without a rush of every
         // wave on the same queue counter.  A workgroup's seeds sit in
         // consecutive pages from page 0; the seeded sectors are the front of
-        // their queues, which then start after them.  Seeds after the first
+        // their queues, which in round 0 start after them.  Seeds after the first
         // round whose estimated cost leaves room before the plan's longest
         // item wait one sleep period before loading: the first round (the
         // longest sectors) then loads with less competition for bandwidth,
@@ -269,10 +272,7 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
                         break;
                     }
                 }
-        for (size_t q = 0; q < plan.queues.size(); ++q) {
-            plan.queues[q].first += taken[q];
-            plan.queues[q].count -= taken[q];
-        }
+        for (size_t q = 0; q < plan.queues.size(); ++q) plan.queues[q].seeded = taken[q];
         plan.buckets.push_back(bk);
     }
     for (size_t i = 0; i < full.size();) {

@@ -38,8 +38,8 @@ struct NpduPlacement {
 // Tunable policy of the pooled NPDU launch.
 struct PoolPolicy {
     float waves_per_simd = 0.0f;   // plan occupancy budget (0 = built-in rule)
-    int waves = 0;                 // explicit shape: waves per workgroup (4 or 8; 0 = from the budget)
-    int groups = 0;                // explicit shape: workgroups per CU (1 or 2; 0 = from the budget)
+    int waves = 0;                 // explicit shape: waves per workgroup (0 = from the budget)
+    int groups = 0;                // explicit shape: workgroups per CU (0 = from the budget)
     bool seed_sleep = true;        // seeds with slack before the critical sector wait before loading
     int seed_priority = 3;         // issue priority of the wave running its workgroup's first seed
     std::vector<NpduPlacement> placement;
@@ -87,6 +87,9 @@ int npdu_readings(int32_t* k, int32_t* flags, std::string* err);
 int32_t largest_sector(int32_t n, int32_t m);
 // Windows wider than twice the sector behave exactly like 2 n_s.
 int32_t clamp_k(int32_t k, int32_t n_s);
+// Pooled launch shapes: one workgroup per CU of 4, 8, 12 or 16 waves (one to
+// four per SIMD), or two of 4 waves each owning half of the CU's pages.
+bool valid_pool_shape(int waves, int groups);
 // Coordinates of an NPDU sector of n points with window k in LDS?
 bool npdu_xyz_in_lds(const PoolPolicy& policy, int n, int k);
 

@@ -35,7 +35,8 @@
 namespace afps {
 
 // Points per lane whose loads are in flight together when a sampler copies
-// its sector into LDS.
+// its sector into LDS (the NPDU samplers' LR): 32 for one wave alone on its
+// SIMD; fewer keep the registers small enough for more waves per SIMD.
 constexpr int kLoadRound = 32;
 
 // Algorithm 1 initialises every distance to 1e10 (exact in fp32).
@@ -355,7 +356,7 @@ __device__ __forceinline__ void sector_lds_ready() {
 //   5. the overall maximum is the larger of (2) and (4); the lowest lane
 //      holding it is the lowest block, whose first index is the next sample.
 // Ties therefore go to the lowest index, as in Algorithm 1.
-template <bool SHIFT>
+template <bool SHIFT, int LR = kLoadRound>
 __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restrict__ xyz, int n, int c,
                                                           int k, int cur, int base,
                                                           int32_t* __restrict__ out, uint32_t* lds,
@@ -385,20 +386,20 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
         fz = xyz[3 * cur + 2];
     }
 
-    // Load in rounds of kLoadRound points per lane, every load of a round in
+    // Load in rounds of LR points per lane, every load of a round in
     // flight at once (the rounds are latency bound).  Indices past n read
     // point n-1; records past n are padding (D = 0, never inside a window).
-    for (int j0 = 0; j0 < np; j0 += kLoadRound * 64) {
-        float v[3 * kLoadRound];
+    for (int j0 = 0; j0 < np; j0 += LR * 64) {
+        float v[3 * LR];
 #pragma unroll
-        for (int u = 0; u < kLoadRound; ++u) {
+        for (int u = 0; u < LR; ++u) {
             const int jj = min(j0 + 64 * u + lane, n - 1);
             v[3 * u] = xyz[3 * jj];
             v[3 * u + 1] = xyz[3 * jj + 1];
             v[3 * u + 2] = xyz[3 * jj + 2];
         }
 #pragma unroll
-        for (int u = 0; u < kLoadRound; ++u) {
+        for (int u = 0; u < LR; ++u) {
             const int jj = j0 + 64 * u + lane;
             uint32_t d = jj < n ? init : 0u;
             if (first_full && jj < n) d = min(init, sq_dist_bits(v[3 * u], v[3 * u + 1], v[3 * u + 2], fx, fy, fz));
@@ -519,7 +520,7 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
 // blocks re-reduced two at a time, and, for sectors too large for 16 bytes per point
 // of LDS (XYZ_IN_LDS = false), only D in LDS and the coordinates read from
 // global memory (L2).
-template <int R, bool XYZ_IN_LDS, bool SHIFT>
+template <int R, bool XYZ_IN_LDS, bool SHIFT, int LR = kLoadRound>
 __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restrict__ xyz, int n, int c,
                                                           int k, int cur, int base,
                                                           int32_t* __restrict__ out, uint32_t* lds,
@@ -547,20 +548,20 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
         fz = xyz[3 * cur + 2];
     }
 
-    // Load: rounds of kLoadRound points per lane with every load in flight
+    // Load: rounds of LR points per lane with every load in flight
     // (coordinates are needed in LDS, or for the full first update).
     if (XYZ_IN_LDS || first_full) {
-        for (int j0 = 0; j0 < np; j0 += kLoadRound * 64) {
-            float v[3 * kLoadRound];
+        for (int j0 = 0; j0 < np; j0 += LR * 64) {
+            float v[3 * LR];
 #pragma unroll
-            for (int u = 0; u < kLoadRound; ++u) {
+            for (int u = 0; u < LR; ++u) {
                 const int jj = min(j0 + 64 * u + lane, n - 1);
                 v[3 * u] = xyz[3 * jj];
                 v[3 * u + 1] = xyz[3 * jj + 1];
                 v[3 * u + 2] = xyz[3 * jj + 2];
             }
 #pragma unroll
-            for (int u = 0; u < kLoadRound; ++u) {
+            for (int u = 0; u < LR; ++u) {
                 const int jj = j0 + 64 * u + lane;
                 uint32_t d = jj < n ? init : 0u;
                 if (first_full && jj < n) d = min(init, sq_dist_bits(v[3 * u], v[3 * u + 1], v[3 * u + 2], fx, fy, fz));
@@ -792,7 +793,7 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
 // block (D = 0, never a window point), so block reads need no bounds test.
 // XYZ_IN_LDS = false reads coordinates from global memory (L2) and keeps only
 // D in LDS, for sectors too large for 16 bytes per point.
-template <int R, bool XYZ_IN_LDS>
+template <int R, bool XYZ_IN_LDS, int LR = kLoadRound>
 __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz, int n, int c,
                                                    int k, int cur, int base,
                                                    int32_t* __restrict__ out, uint32_t* lds,
@@ -801,15 +802,15 @@ __device__ __forceinline__ void sample_sector_npdu(const float* __restrict__ xyz
     const bool shift = (flags & kNpduShiftEdges) != 0;
     if constexpr (R == 1 && XYZ_IN_LDS) {
         if (k <= 64) {   // the window lies in two adjacent blocks
-            if (shift) sample_sector_npdu_narrow<true>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
-            else sample_sector_npdu_narrow<false>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
+            if (shift) sample_sector_npdu_narrow<true, LR>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
+            else sample_sector_npdu_narrow<false, LR>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
             return;
         }
     }
     if (shift)
-        sample_sector_npdu_blocks<R, XYZ_IN_LDS, true>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
+        sample_sector_npdu_blocks<R, XYZ_IN_LDS, true, LR>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
     else
-        sample_sector_npdu_blocks<R, XYZ_IN_LDS, false>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
+        sample_sector_npdu_blocks<R, XYZ_IN_LDS, false, LR>(xyz, n, c, k, cur, base, out, lds, first_full, t_loaded);
 }
 
 }  // namespace afps

@@ -47,18 +47,27 @@ struct SectorStamp {
 };
 static_assert(sizeof(SectorStamp) == 64, "sector stamp layout");
 
-// Arguments of the pooled NPDU kernel (passed by value).
-struct PoolArgs {
+// Inputs and outputs of one round of a launch of several rounds (one DEVICE
+// entry per round; the same layout as afps_round in afps.h).
+struct PoolRound {
     const float* xyz_all;
     int32_t* out_all;
+};
+static_assert(sizeof(PoolRound) == 16, "round layout");
+
+// Arguments of the pooled NPDU kernel (passed by value).
+struct PoolArgs {
+    const float* xyz_all;      // a single round's points and outputs (rounds == nullptr)
+    int32_t* out_all;
+    const PoolRound* rounds;   // several rounds: per-round points and outputs, or nullptr
     const WorkItem* items;
     const PoolQueue* queues;
-    unsigned* qtaken;          // one counter per queue
+    unsigned* qtaken;          // queue counters, kRoundCounters per round
     const PoolSeed* seeds;
     unsigned* status;          // the plan's status word (workspace), set when a wave gives up
     unsigned* dev_status;      // the device's failure word, set alike
-    SectorStamp* stamps;       // per plan item, or nullptr
-    int nq, seed_groups, pool_pages;
+    SectorStamp* stamps;       // per plan item (single round only), or nullptr
+    int nrounds, nq, seed_groups, pool_pages;
     unsigned spin_limit;
     int seed_priority;         // issue priority (0..3) of the wave running its workgroup's first seed
 };

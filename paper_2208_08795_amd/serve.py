@@ -107,6 +107,7 @@ class Batch:
     ws_bytes: int = 0          # size of the arena block reserved for the plan's workspace
     handle: object = None
     launched: float = None
+    kernel_ms: float = None    # the sampling launches' own time (HIP events), when the executor times them
 
 
 class Scheduler:
@@ -125,6 +126,9 @@ class Scheduler:
         self.finished = []
         self.peak_bytes = 0
         self.peak_waiting = 0
+        self.batch_log = []            # completed batches, in completion order
+        self.left_waiting = 0          # frames still waiting when a time window closed
+        self.oldest_wait_s = 0.0       # how long the oldest of them had waited then
 
     def _fits_ever(self, req) -> bool:
         p, o = footprint(req)
@@ -191,10 +195,9 @@ class Scheduler:
                 self.arena.free(req.out_off)
         self.arena.free(batch.ws_off)
 
-    def step(self):
-        """Complete finished batches, then admit and launch. Returns True if anything moved."""
+    def _complete(self):
+        """Finish the batches whose completion event has fired; True if any did."""
         moved = False
-        now = self.clock()
         for batch in list(self.inflight):
             if self.ex.done(batch.handle):
                 t = self.clock()
@@ -208,7 +211,14 @@ class Scheduler:
                     self.finished.append(req)
                 self._release(batch)
                 self.inflight.remove(batch)
+                self.batch_log.append(batch)
                 moved = True
+        return moved
+
+    def step(self):
+        """Complete finished batches, then admit and launch. Returns True if anything moved."""
+        now = self.clock()
+        moved = self._complete()
         while True:
             batch = self._admit(now)
             if batch is None:
@@ -225,8 +235,12 @@ class Scheduler:
             moved = True
         return moved
 
-    def run(self, requests, idle_sleep: float = 0.0):
-        """Feed requests at their arrival times (seconds after the start) until all finish."""
+    def run(self, requests, idle_sleep: float = 0.0, window: float | None = None):
+        """Feed requests at their arrival times (seconds after the start) until
+        all finish, or, with `window`, until that many seconds have passed:
+        then frames not yet arrived are dropped, frames still waiting stay in
+        self.waiting (counted in left_waiting, the longest wait in
+        oldest_wait_s) and the batches on the device complete."""
         pending = sorted(requests, key=lambda r: r.arrival)
         t0 = self.clock()
         for r in pending:
@@ -234,6 +248,14 @@ class Scheduler:
         i = 0
         while i < len(pending) or self.waiting or self.inflight:
             now = self.clock()
+            if window is not None and now - t0 >= window:
+                self.left_waiting = len(self.waiting)
+                self.oldest_wait_s = max((now - r.arrival for r in self.waiting), default=0.0)
+                while self.inflight:
+                    self.clock()
+                    if not self._complete() and idle_sleep:
+                        time.sleep(idle_sleep)
+                break
             while i < len(pending) and pending[i].arrival <= now:
                 self.submit(pending[i])
                 i += 1
@@ -251,7 +273,7 @@ class GpuExecutor:
     (e.g. to record timing events around them)."""
 
     def __init__(self, arena_bytes: int, streams: int = 4, keep_results: bool = False,
-                 device="cuda", on_launch=None):
+                 device="cuda", on_launch=None, timing: bool = False):
         import torch
 
         from . import binding
@@ -264,6 +286,7 @@ class GpuExecutor:
         self.next = 0
         self.keep = keep_results
         self.on_launch = on_launch
+        self.timing = timing           # HIP events around each batch's sampling launches
 
     def _points_view(self, req):
         t = self.torch
@@ -283,6 +306,10 @@ class GpuExecutor:
                 self._points_view(req).copy_(req.points, non_blocking=True)
             fps = [r for r in reqs if r.m == 1 and r.k is None]
             rest = [r for r in reqs if not (r.m == 1 and r.k is None)]
+            ev0 = ev1 = None
+            if self.timing:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(s)
             sh = ctypes.c_void_p(s.cuda_stream)
             if rest:
                 descs = (B.CloudDesc * len(rest))()
@@ -302,13 +329,16 @@ class GpuExecutor:
             for r in fps:
                 B._check(self.L.afps_fps_plain(ctypes.c_void_p(self.base + r.pts_off), r.n, r.c,
                                                r.start, ctypes.c_void_p(self.base + r.out_off), sh))
+            if self.timing:
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev1.record(s)
             if self.on_launch is not None:
                 self.on_launch(s, batch)
             for r in reqs:
                 self._host_view(r).copy_(self._out_view(r), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        return (ev, plan)
+        return (ev, plan, ev0, ev1)
 
     def _host_view(self, req):
         return self.host[req.out_off:req.out_off + 4 * req.c].view(self.torch.int32)
@@ -319,7 +349,9 @@ class GpuExecutor:
     def finish(self, batch: Batch):
         """The batch's event has fired: destroy its plan and return
         {rid: error} for the frames whose indices hold -1."""
-        ev, plan = batch.handle
+        ev, plan, ev0, ev1 = batch.handle
+        if ev0 is not None:
+            batch.kernel_ms = ev0.elapsed_time(ev1)
         failed = {}
         for r in batch.requests:
             v = self._host_view(r).numpy()

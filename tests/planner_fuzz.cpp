@@ -53,8 +53,10 @@ PlannerEnv make_env(std::mt19937_64& rng, const std::vector<FakeVariant>& vars) 
     const float occ[] = {0.0f, 1.0f, 1.5f, 2.0f, 4.0f};
     env.pool.waves_per_simd = occ[std::uniform_int_distribution<int>(0, 4)(rng)];
     if (std::uniform_int_distribution<int>(0, 2)(rng) == 0) {
-        env.pool.waves = std::uniform_int_distribution<int>(0, 1)(rng) ? 4 : 8;
-        env.pool.groups = std::uniform_int_distribution<int>(1, 2)(rng);
+        const int shapes[][2] = {{4, 1}, {8, 1}, {4, 2}, {8, 2}, {12, 1}, {16, 1}};
+        const auto& sh = shapes[std::uniform_int_distribution<int>(0, 5)(rng)];
+        env.pool.waves = sh[0];
+        env.pool.groups = sh[1];
     }
     env.pool.seed_sleep = std::uniform_int_distribution<int>(0, 1)(rng) != 0;
     env.pool.seed_priority = std::uniform_int_distribution<int>(0, 3)(rng);
@@ -166,7 +168,7 @@ void check_plan(const std::vector<afps_cloud_desc>& d, const PlannerEnv& env, co
         if (bk.pool()) {
             ++pool_buckets;
             CHECK(bk.first == 0, "pool bucket first");
-            CHECK(bk.block == 64 * t.pool_waves && (t.pool_waves == 4 || t.pool_waves == 8), "pool waves");
+            CHECK(bk.block == 64 * t.pool_waves && valid_pool_shape(t.pool_waves, t.pool_groups), "pool shape");
             CHECK(bk.lds_bytes == t.pool_pages * kPoolPageBytes, "pool LDS");
             CHECK(t.pool_groups == 1 || t.pool_groups == 2, "pool groups");
             CHECK(t.pool_pages >= 1 && t.pool_pages * t.pool_groups <= env.cu_pool_pages, "pool pages");
@@ -182,15 +184,23 @@ void check_plan(const std::vector<afps_cloud_desc>& d, const PlannerEnv& env, co
     for (const auto& it : t.items) npdu_items += it.k >= 0;
     CHECK((int)t.queues.size() <= kMaxPoolQueues, "queues");
     std::vector<int> seen(t.items.size(), 0);
+    std::vector<int> in_queue(t.items.size(), 0);
+    int next_first = 0;
     for (const auto& q : t.queues) {
-        CHECK(q.first >= 0 && q.count >= 0 && q.first + q.count <= npdu_items, "queue range");
+        CHECK(q.first >= 0 && q.count >= 1 && q.first + q.count <= npdu_items, "queue range");
+        CHECK(q.seeded >= 0 && q.seeded <= q.count, "queue seeded %d of %d", q.seeded, q.count);
         CHECK(q.pages >= 1 && q.pages <= t.pool_pages, "queue pages %d of %d", q.pages, t.pool_pages);
+        CHECK(q.first == next_first, "queues tile the NPDU items in order");
+        next_first = q.first + q.count;
         for (int i = q.first; i < q.first + q.count && i < (int)t.items.size(); ++i) {
-            ++seen[i];
+            ++in_queue[i];
+            if (i >= q.first + q.seeded) ++seen[i];   // round 0 queues only the unseeded ones
             const WorkItem& it = t.items[i];
             CHECK(npdu_pool_pages(it.n, npdu_item_xyz_in_lds(it.n, it.flags)) == q.pages, "item pages");
         }
     }
+    CHECK(next_first == npdu_items, "queues cover the NPDU items");
+    for (int i = 0; i < npdu_items; ++i) CHECK(in_queue[i] == 1, "NPDU item %d in %d queues (later rounds)", i, in_queue[i]);
     if (npdu_items) {
         const int waves = t.pool_waves;
         CHECK((int)t.seeds.size() % waves == 0, "seed table shape");
@@ -202,6 +212,9 @@ void check_plan(const std::vector<afps_cloud_desc>& d, const PlannerEnv& env, co
                 const PoolSeed& sd = t.seeds[(size_t)g * waves + w];
                 if (sd.item < 0) continue;
                 CHECK(sd.item < npdu_items, "seed item");
+                bool front = false;   // a seed is among the first `seeded` items of its queue
+                for (const auto& q : t.queues) front |= sd.item >= q.first && sd.item < q.first + q.seeded;
+                CHECK(front, "seed %d is not at the front of its queue", sd.item);
                 if (sd.item >= npdu_items) continue;
                 ++seen[sd.item];
                 const WorkItem& it = t.items[sd.item];

@@ -87,7 +87,8 @@ def test_host_validation_without_gpu(L):
     assert L.afps_plan_launch_noalloc(None, dummy, dummy, None) == -1
     assert L.afps_plan_status(None, dummy, None) == -1
     assert L.afps_plan_launch_stamped(None, dummy, dummy, dummy, dummy, 64, None) == -1
-    assert L.afps_noalloc_max_items() == ((1 << 20) - 35584) // 40
+    header = 256 + 128 * 4 + 128 * 16 + 512 * 16 * 8   # counters, queue table, seeds (512 groups x 16 waves)
+    assert L.afps_noalloc_max_items() == ((1 << 20) - header) // 40
     # grouping: arguments checked on the host; no centres launches nothing
     assert L.afps_ball_query(None, 10, dummy, 4, 1.0, 8, -1, dummy, None, None) == -1
     assert L.afps_ball_query(dummy, 10, None, 4, 1.0, 8, -1, dummy, None, None) == -1

@@ -105,3 +105,97 @@ def test_stamped_launch_is_exact_and_its_stamps_are_consistent(env, batch256):
     print("cycles per iteration: median %.0f, max %.0f" % (np.median(cyc), cyc.max()), flush=True)
     assert 100 < np.median(cyc) < 5000
     plan.close()
+
+
+def test_rounds_in_one_launch_equal_separate_launches(env):
+    """Several rounds of one plan in one pooled launch, alternating two inputs
+    of the same layout, every round writing its own output: each round equals
+    a separate launch of the plan on that input (and the oracle on samples);
+    one round equals afps_plan_launch; a graph capture replays exactly."""
+    torch, B, dev = env
+    sizes = [int(n) for n in np.exp(np.random.default_rng(4).uniform(np.log(1024), np.log(32768), 48)).round()]
+    cs = [n // 4 for n in sizes]
+    inputs = []
+    for seed in (0, 1):
+        clouds = [synth.object_cloud(n, seed=1000 * seed + i) for i, n in enumerate(sizes)]
+        inputs.append((clouds, torch.from_numpy(np.concatenate(clouds)).to(dev)))
+    plan = B.BatchPlan(sizes, cs, [8] * 48, [32] * 48, [0] * 48, device=dev)
+    want = []
+    for clouds, xyz in inputs:
+        want.append(plan.launch(xyz).clone())
+    torch.cuda.synchronize()
+    for i in (0, 17, 47):
+        o = plan.offsets[i]
+        assert np.array_equal(want[1][o:o + cs[i]].cpu().numpy(), oracle.afps(inputs[1][0][i], cs[i], 8, 32, 0)), i
+    for count in (1, 2, 7):
+        outs = [torch.full((plan.total_samples,), -7, dtype=torch.int32, device=dev) for _ in range(count)]
+        rounds = [(inputs[r % 2][1], outs[r]) for r in range(count)]
+        print("rounds: %d" % count, flush=True)
+        table = plan.launch_rounds(rounds)
+        torch.cuda.synchronize()
+        plan.status()
+        for r in range(count):
+            assert torch.equal(outs[r], want[r % 2]), (count, r)
+    # a captured launch of several rounds, replayed with eager work in between
+    outs = [torch.full((plan.total_samples,), -7, dtype=torch.int32, device=dev) for _ in range(3)]
+    table = plan.round_table([(inputs[r % 2][1], outs[r]) for r in range(3)])
+    plan.launch_rounds(table)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.launch_rounds(table, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        torch.zeros(1000, device=dev).sum().item()
+        for r in range(3):
+            assert torch.equal(outs[r], want[r % 2]), ("graph", rep, r)
+    plan.close()
+
+
+def test_rounds_forced_timeouts_fail_whole_sectors(env):
+    """A spin limit of 1 in a launch of several rounds: every sector of every
+    round is exact or entirely -1, the plan reports the failure, and the next
+    launch of several rounds is exact again."""
+    torch, B, dev = env
+    clouds = synth.batch_of_objects(64, seed=9, n_min=2048, n_max=32768)
+    sizes, cs = [len(p) for p in clouds], [len(p) // 4 for p in clouds]
+    xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    plan = B.BatchPlan(sizes, cs, [8] * 64, [32] * 64, [0] * 64, device=dev)
+    want = plan.launch(xyz).clone().cpu().numpy()
+    outs = [torch.full((plan.total_samples,), -7, dtype=torch.int32, device=dev) for _ in range(3)]
+    table = plan.round_table([(xyz, o) for o in outs])
+    B.clear_device_status()
+    B.set_spin_limit(1)
+    try:
+        plan.launch_rounds(table)
+        torch.cuda.synchronize()
+    finally:
+        B.set_spin_limit(1 << 22)
+    failed = 0
+    for o in outs:
+        got = o.cpu().numpy()
+        failed += int((got == -1).sum())
+        for i, c in enumerate(cs):
+            base = plan.offsets[i]
+            for s_ in range(8):
+                lo = base + s_ * (c // 8) + min(s_, c % 8)
+                cc = c // 8 + (s_ < c % 8)
+                sector = got[lo:lo + cc]
+                assert np.array_equal(sector, want[lo:lo + cc]) or np.all(sector == -1), (i, s_)
+    if failed:
+        with pytest.raises(B.AfpsError):
+            plan.status()
+    B.clear_device_status()
+    plan.launch_rounds(table)
+    torch.cuda.synchronize()
+    plan.status()
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy(), want)
+    plan.close()

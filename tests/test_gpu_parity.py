@@ -575,20 +575,21 @@ def test_pooled_sectors_with_tuned_coordinate_placement(B, torch_dev, placement)
             B.tune_npdu(2048, 1 << 30, True)
             B.tune_npdu(8192, 1 << 30, False)
         assert B.npdu_xyz_in_lds(1000, 32) == (placement == "l2_above_2048")
-        assert B.npdu_xyz_in_lds(5000, 32) == False
+        assert B.npdu_xyz_in_lds(5000, 32) == (placement == "l2_up_to_2048")
         sizes = [4096, 4097, 2048, 2049, 8192, 777, 65, 1, 3000, 6000, 12000, 1500]
         ms = [1, 1, 1, 1, 1, 1, 1, 1, 2, 3, 2, 1]
         ks = [32, 64, 8, 100, 32, 0, 65, 0, 200, 17, 33, 64]
         cs = [max(m, n // 5) for n, m in zip(sizes, ms)]
         starts = [0, 4096, 7, 2048, 8191, 3, 64, 0, 2999, 5, 11999, 700]
         flags = [0, 1, 2, 3, 0, 2, 0, 0, 1, 0, 2, 3]
-        clouds = [synth.object_cloud(n, seed=i) if i % 2 else synth.uniform_cube(n, seed=i) for i, n in enumerate(sizes)]
+        clouds = [synth.object_cloud(n, seed=i) if i % 2 and n >= 64 else synth.uniform_cube(n, seed=i)
+                  for i, n in enumerate(sizes)]
         _batch_case(B, torch, dev, clouds, cs, ms, ks, starts, graph_replays=2, flags=flags)
     finally:
         B.tune_reset()
 
 
-@pytest.mark.parametrize("shape", [(4, 1), (8, 1), (4, 2)])
+@pytest.mark.parametrize("shape", [(4, 1), (8, 1), (4, 2), (12, 1), (16, 1)])
 @pytest.mark.parametrize("seeding", [(False, 0), (True, 3)])
 def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
     """Every pooled launch shape and seeding policy the tuner can pick, on
@@ -600,5 +601,25 @@ def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
     try:
         plan = _batch_case(B, torch, dev, clouds, cs, [8] * 40, [32] * 40, [0] * 40, graph_replays=1)
         assert (plan.pool_waves, plan.pool_groups) == shape
+    finally:
+        B.tune_reset()
+
+
+def test_npdu_tuner_choices_stay_exact(B, torch_dev):
+    """The NPDU tuner times every pooled launch shape, coordinate placement
+    and seeding policy on a batch (one launch of several rounds each), checks
+    that each gives the same indices, and installs the fastest: a plan built
+    afterwards is exact against the oracle."""
+    torch, dev = torch_dev
+    from paper_2208_08795_amd import autotune
+    clouds = synth.batch_of_objects(32, seed=33, n_min=1024, n_max=32768)
+    sizes, cs = [len(p) for p in clouds], [len(p) // 4 for p in clouds]
+    xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    try:
+        res = autotune.tune_npdu(xyz, sizes, cs, [8] * 32, [32] * 32, [0] * 32, rounds=3, reps=1)
+        print("npdu tuner best", res["best"], "of", len(res["rows"]), flush=True)
+        assert len(res["rows"]) >= 3 * len(autotune.L2_UP_TO)
+        plan = _batch_case(B, torch, dev, clouds, cs, [8] * 32, [32] * 32, [0] * 32, graph_replays=1)
+        assert (plan.pool_waves, plan.pool_groups) == res["best"][0]
     finally:
         B.tune_reset()

@@ -136,3 +136,18 @@ def test_device_side_failure_marks_only_its_frames_failed():
     from paper_2208_08795_amd.serve import latency_summary
     summ = latency_summary(list(done.values()))
     assert summ["failed"] == 2 and summ["frames"] == 7
+
+
+def test_time_window_stops_admission_and_reports_the_queue():
+    """A window shorter than the stream: frames still waiting are reported
+    (count and the oldest one's wait), frames on the device complete, frames
+    that had not arrived are dropped."""
+    clock = FakeClock(dt=1e-4)
+    ex = FakeExecutor(clock)
+    s = Scheduler(ex, 4 << 20, max_inflight=1, max_batch=1, clock=clock)
+    reqs = [_req(i, 60000, 0.0005 * i) for i in range(200)]     # 1 ms of work each, arriving every 0.5 ms
+    done = s.run(reqs, window=0.05)
+    assert all(r.state == "done" for r in done)
+    assert 20 <= len(done) <= 60
+    assert s.left_waiting > 10 and s.oldest_wait_s > 0.01
+    assert not s.inflight and len(s.waiting) == s.left_waiting
