@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import gc
 import hashlib
 import json
 import math
@@ -132,13 +133,16 @@ def stamp_cycles(stamps, wall_khz):
     ok = c > 1
     cyc = (end - loaded)[ok] / (c[ok] - 1)
     ghz = float((end - take).sum() / (end_rt - take_rt).sum() * wall_khz * 1e-6) if wall_khz else None
-    crit = int(np.argmax(end - take.min()))
+    # shader-clock counters differ between XCDs: compare sectors on the
+    # constant-rate counter only (the launch's first take to each sector's end)
+    crit = int(np.argmax(end_rt))
     return {"median": round(float(np.median(cyc)), 1), "p10": round(float(np.percentile(cyc, 10)), 1),
             "p90": round(float(np.percentile(cyc, 90)), 1),
             "critical_sector": {"points": int(n[crit]), "samples": int(c[crit]),
                                 "cycles_per_iteration": round(float((end[crit] - loaded[crit]) / max(1, c[crit] - 1)), 1),
                                 "load_us": round(float((loaded[crit] - take[crit]) / (ghz * 1e3)), 2) if ghz else None,
-                                "ends_at_us": round(float((end[crit] - take.min()) / (ghz * 1e3)), 1) if ghz else None},
+                                "ends_at_us": round(float((end_rt[crit] - take_rt.min()) / (wall_khz * 1e-3)), 1)
+                                if wall_khz else None},
             "by_points": {label: round(float(np.median(cyc[(n[ok] > lo) & (n[ok] <= hi)])), 1)
                           for label, lo, hi in (("<=1024", 0, 1024), ("1025-2048", 1024, 2048),
                                                 ("2049-4096", 2048, 4096))
@@ -392,8 +396,14 @@ def serving(torch, ops_fn, rates=(50, 200, 800), seconds=10.0, max_frames=2000, 
             m, k = (f.m, f.k) if method == "afps_npdu" else (1, None)
             reqs.append(Request(i, f.points.shape[0], f.c, m, k, 0, float(arr[i]), pinned[i % pool]))
         s = Scheduler(ex, budget, max_inflight=8, max_batch=32)
-        done = s.run(reqs, window=window)
-        torch.cuda.synchronize()
+        # a serving loop keeps the collector out of its frames' latency
+        gc.collect()
+        gc.disable()
+        try:
+            done = s.run(reqs, window=window)
+            torch.cuda.synchronize()
+        finally:
+            gc.enable()
         out = latency_summary(done)
         out.update({"offered_fps": lam, "offered_frames": count, "peak_waiting": s.peak_waiting,
                     "peak_arena_bytes": s.peak_bytes})
@@ -573,20 +583,25 @@ def main():
     l2_up_to = max((n for n in range(64, 8193, 64) if not binding.npdu_xyz_in_lds(n, K)), default=0)
     log("AFPS-NPDU plan: %d sectors, %s, coordinates in L2 up to %d points" % (plan.items, label, l2_up_to))
 
-    # reference: one eager pass (checked against the oracle by cpu_baseline)
-    ref = plan.launch(xyz_all, stream=stream)
-    torch.cuda.synchronize()
-    out_np = ref.cpu().numpy()
-
-    # ---- the timed steps: one launch of K rounds, each round its own output
+    # ---- the timed steps: one launch of K rounds, each round its own output;
+    # the warm-up launch (W rounds) writes a reference of its own
     steps, warm = args.steps, args.warmup
     outs = torch.full((steps, plan.total_samples), -7, dtype=torch.int32, device=dev)
     inputs = (xyz_all, xyz_copy)
     table = plan.round_table([(inputs[r % 2], outs[r]) for r in range(steps)])
-    if warm:
-        wtable = plan.round_table([(inputs[r % 2], outs[r % steps]) for r in range(warm)])
-        plan.launch_rounds(wtable, stream=stream)
+    wouts = torch.full((max(1, warm), plan.total_samples), -7, dtype=torch.int32, device=dev)
+    wtable = plan.round_table([(inputs[r % 2], wouts[r]) for r in range(max(1, warm))])
+    plan.launch_rounds(wtable, stream=stream)
     torch.cuda.synchronize()
+    ref = wouts[0].clone()
+    out_np = ref.cpu().numpy()          # checked against the oracle by cpu_baseline
+    if not bool((wouts == ref.unsqueeze(0)).all()):
+        raise SystemExit("bench: the warm-up rounds' indices differ")
+    if not args.only_timed:             # and against a separate single pass
+        single = plan.launch(xyz_all, stream=stream)
+        torch.cuda.synchronize()
+        if not torch.equal(single, ref):
+            raise SystemExit("bench: a round's indices differ from a single pass")
     ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev_a.record(stream)
@@ -598,7 +613,7 @@ def main():
     sclk = shader_clock_mhz()
     plan.status(stream=stream)
     if not bool((outs == ref.unsqueeze(0)).all()):
-        raise SystemExit("bench: a round's indices differ from the single pass")
+        raise SystemExit("bench: a timed round's indices differ from the warm-up's")
     ms_per_step = wall * 1e3 / steps
     value = total_samples * steps / wall
     log("AFPS-NPDU: %d rounds in one launch, %.4f ms/step (launch %.3f ms), %.3e sampled pts/s" %

@@ -61,11 +61,14 @@ def test_stamp_cycles_reduction():
     for item, (n, c, take, loaded, end) in enumerate([(4096, 101, 0, 600, 10600), (1000, 11, 100, 300, 2300)]):
         pairs = np.array([item, n, c, 32, 0, 0], dtype=np.int32).view(np.int64)
         rows.append([take, loaded, end, take // 20, end // 20] + list(pairs))
+    # the second sector ran on another XCD whose shader clock reads far ahead
+    rows[1][:3] = [v + 10 ** 9 for v in rows[1][:3]]
     st = torch.tensor(rows, dtype=torch.int64)
     r = bench.stamp_cycles(st, 100000)
     assert r["median"] == 150.0 and r["sclk_ghz"] == 2.0
     assert r["critical_sector"]["points"] == 4096 and r["critical_sector"]["cycles_per_iteration"] == 100.0
     assert r["critical_sector"]["load_us"] == 0.3
+    assert r["critical_sector"]["ends_at_us"] == 5.3     # on the constant-rate counter: 530 ticks at 100 MHz
 
 
 def test_host_readers_return_plain_values():
