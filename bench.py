@@ -109,8 +109,9 @@ def fps_ops(sizes, cs):
 
 def counter_record(label):
     """Per-round SQ / traffic counters of the pooled kernel in `label`'s launch
-    layout from the committed rocprofv3 record, or None when the kernel
-    sources changed since or that layout was not profiled."""
+    layout and coordinate placement from the committed rocprofv3 record, or
+    None when the kernel or plan sources changed since or that layout was not
+    profiled."""
     path = os.path.join(ROOT, "profiles", "pooled_npdu_kernel_batch256_counters.json")
     if not os.path.exists(path):
         return None
@@ -653,7 +654,7 @@ def main():
     hbm_round = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
     lds_round = 20 * cnt["updates"]              # 16 B read (x, y, z, D) + 4 B written per update
     lds_peak_tbs = CUS * LDS_BYTES_PER_CLK_PER_CU * clock_ghz * 1e9 / 1e12
-    rec = counter_record(label)
+    rec = counter_record("%s, L2 up to %d" % (label, l2_up_to))
     roof = {"bound": "alu", "kernel": label, "achieved": ops_launch / launch_s / 1e12, "peak": VALU_PEAK_TOPS,
             "unit": "TOPS (fp32 VALU lane-ops)", "frac": ops_launch / launch_s / 1e12 / VALU_PEAK_TOPS,
             "traffic": (int(rec["traffic_bytes_per_round"] * steps) if rec and rec.get("traffic_bytes_per_round")
