@@ -534,8 +534,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuners (built-in rules)")
     ap.add_argument("--pool", type=str, default=None,
                     help="pooled launch shape 'waves,groups' for the timed batch (skips its tuning)")
-    ap.add_argument("--l2-up-to", type=int, default=None,
-                    help="NPDU sectors of at most this many points read coordinates from L2 (with --pool)")
+    ap.add_argument("--regs-up-to", type=int, default=None,
+                    help="NPDU sectors of at most this many points hold their coordinates out of LDS "
+                         "(registers), larger ones in LDS (with --pool; 0 = all in LDS)")
     ap.add_argument("--only-timed", action="store_true",
                     help="stop after the timed launch (for profiler runs: warm-up and timed launches only)")
     args = ap.parse_args()
@@ -572,8 +573,10 @@ def main():
     if args.pool is not None:
         w, g = (int(x) for x in args.pool.split(","))
         binding.set_pool_policy(w, g, True, 3)
-        if args.l2_up_to:
-            binding.tune_npdu(args.l2_up_to, K, False)
+        if args.regs_up_to is not None:
+            if args.regs_up_to:
+                binding.tune_npdu(args.regs_up_to, K, False)
+            binding.tune_npdu(8192, K, True)
     elif not args.no_tune:
         log("tuning the pooled NPDU launch on the batch")
         res_tune = autotune.tune_npdu(xyz_all, sizes, cs, [M] * 256, [K] * 256, [0] * 256, rounds=20, log=log)
@@ -581,8 +584,8 @@ def main():
     label = "pooled_npdu_kernel<%d>" % plan.pool_waves
     if plan.pool_groups > 1:
         label += " x%d per CU" % plan.pool_groups
-    l2_up_to = max((n for n in range(64, 8193, 64) if not binding.npdu_xyz_in_lds(n, K)), default=0)
-    log("AFPS-NPDU plan: %d sectors, %s, coordinates in L2 up to %d points" % (plan.items, label, l2_up_to))
+    regs_up_to = max((n for n in range(64, 8193, 64) if not binding.npdu_xyz_in_lds(n, K)), default=0)
+    log("AFPS-NPDU plan: %d sectors, %s, coordinates out of LDS up to %d points" % (plan.items, label, regs_up_to))
 
     # ---- the timed steps: one launch of K rounds, each round its own output;
     # the warm-up launch (W rounds) writes a reference of its own
@@ -628,15 +631,15 @@ def main():
                                   "pooled launch of K rounds of the batch (alternating two resident inputs, "
                                   "one output per round)" % (sum(sizes), total_samples),
                       "clouds": 256, "m": M, "k": K, "points": sum(sizes), "samples": total_samples,
-                      "pool_launch": label, "coordinates_in_l2_up_to_points": l2_up_to}}
+                      "pool_launch": label, "coordinates_out_of_lds_up_to_points": regs_up_to}}
     if res_tune is not None:
-        res["npdu_tuning"] = {"best": {"shape": list(res_tune["best"][0]), "l2_up_to": res_tune["best"][1],
+        res["npdu_tuning"] = {"best": {"shape": list(res_tune["best"][0]), "regs_up_to": res_tune["best"][1],
                                        "seed_sleep": res_tune["best"][2][0], "seed_priority": res_tune["best"][2][1],
                                        "ms_per_step": round(res_tune["best"][3], 4)},
                               "rows": [[list(r[0]), r[1], list(r[2]), round(r[3], 4)] for r in res_tune["rows"]],
                               "seconds": round(res_tune["seconds"], 2),
                               "what": "ms per batch in one launch of 20 rounds, per pooled launch shape "
-                                      "(waves, workgroups per CU), L2 placement bound and seeding (sleep, priority)"}
+                                      "(waves, workgroups per CU), bound of coordinates out of LDS and seeding (sleep, priority)"}
     res["sclk_mhz_after_timed_steps"] = sclk
 
     # ---- roofline of the dominant kernel, on the timed launch's own time
@@ -654,7 +657,7 @@ def main():
     hbm_round = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
     lds_round = 20 * cnt["updates"]              # 16 B read (x, y, z, D) + 4 B written per update
     lds_peak_tbs = CUS * LDS_BYTES_PER_CLK_PER_CU * clock_ghz * 1e9 / 1e12
-    rec = counter_record("%s, L2 up to %d" % (label, l2_up_to))
+    rec = counter_record("%s, registers up to %d" % (label, regs_up_to))
     roof = {"bound": "alu", "kernel": label, "achieved": ops_launch / launch_s / 1e12, "peak": VALU_PEAK_TOPS,
             "unit": "TOPS (fp32 VALU lane-ops)", "frac": ops_launch / launch_s / 1e12 / VALU_PEAK_TOPS,
             "traffic": (int(rec["traffic_bytes_per_round"] * steps) if rec and rec.get("traffic_bytes_per_round")

@@ -153,44 +153,47 @@ typedef struct afps_plan afps_plan;
 /*
  * Build a batch plan on the host from `batch` HOST descriptors: validates
  * them, expands every cloud into its sectors (work items), orders the items
- * longest-first, and groups them: NPDU sectors into queues by LDS pages (one
- * pooled launch), FPS/AFPS sectors by kernel variant (one persistent launch
- * each); sizes the workspace.
+ * longest-first, and groups them: NPDU sectors are each assigned to one
+ * workgroup of the pooled launch (balanced by estimated cost) and queued
+ * there by LDS pages, FPS/AFPS sectors are grouped by kernel variant (one
+ * persistent launch each); sizes the workspace.
  * Returns AFPS_OK and *plan, or an error (AFPS_ERR_ARG names the first bad
  * descriptor in afps_last_error()).
  */
 int afps_plan_create(const afps_cloud_desc *descs, int32_t batch, afps_plan **plan);
 
-/* Device workspace bytes the plan needs (counters, queue and seed tables, work items). */
+/* Device workspace bytes the plan needs (counters, workgroup, seed and queue tables, work items). */
 size_t afps_plan_workspace_bytes(const afps_plan *plan);
 
 /*
  * Workspace bytes of a plan with `items` work items in total (one per sector,
- * i.e. the sum of m over the batch): a 66.75 KB header of queue counters, the
- * NPDU queue table and the table of each pooled wave's first sector, plus 40
- * bytes per item, rounded up to 256.  Lets a caller reserve device memory before building
- * the plan.  Host-only arithmetic; 0 for items <= 0.
+ * i.e. the sum of m over the batch): a 68.25 KB header (the launch counters,
+ * the pooled workgroups' queue ranges and each pooled wave's first sector),
+ * then 40 bytes per item and at most one 16-byte NPDU queue per item, rounded
+ * up to 256.  Lets a caller reserve device memory before building the plan.
+ * Host-only arithmetic; 0 for items <= 0.
  */
 size_t afps_workspace_bytes_for_items(int32_t items);
 
 /*
- * Copy the plan's tables (NPDU queues and first sectors, work items) into `workspace` (DEVICE,
+ * Copy the plan's tables (NPDU workgroups, queues and first sectors, work items) into `workspace` (DEVICE,
  * >= the size above, 256-byte aligned) on `stream`, asynchronously.  Must precede
  * afps_plan_launch with that workspace in stream order: a launch on another
  * stream is ordered after the copy by the caller (an event, or a stream that
  * waits for this one); the tables stay valid until overwritten.  A plan's
  * launches on several streams at once each need their own workspace (its
- * queue counters are reset and consumed by every launch).
+ * launch counters and status word are reset and used by every launch).
  */
 int afps_plan_upload(afps_plan *plan, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Run the batch: reset the queue counters (a kernel), then one persistent
+ * Run the batch: reset the launch counters (a kernel), then one persistent
  * launch per kernel variant, concurrent on helper streams when there are
- * several; workgroups (NPDU: waves) take work items from device queues with
- * atomic counters until the queues are empty.  Kernel launches only, so a
- * caller may capture it in a hipGraph.  Launches with one workspace must not
- * overlap.
+ * several.  FPS/AFPS workgroups take work items from device queues with
+ * atomic counters until the queues are empty; the waves of a pooled NPDU
+ * workgroup take its own sectors, claimed in its LDS.  Kernel launches only,
+ * so a caller may capture it in a hipGraph.  Launches with one workspace must
+ * not overlap.
  */
 int afps_plan_launch(const afps_plan *plan, const float *xyz_all, int32_t *out_all,
                      void *workspace, void *stream);
@@ -209,14 +212,15 @@ int afps_plan_graph_launch(afps_plan *plan, const float *xyz_all, int32_t *out_a
  * processed back to back on the device with no kernel boundary between
  * them.  Round r reads rounds[r].xyz_all and writes rounds[r].out_all (both
  * laid out as for afps_plan_launch).  Each wave takes the highest-priority
- * sector that fits its workgroup's free LDS pages from the lowest round with
- * sectors left, or from the next round when none of that one fits, so the
- * next batch's sectors start as soon as pages free up.  Every output of every
- * round is the same as a separate afps_plan_launch of that round gives.
+ * of its workgroup's sectors that fits the workgroup's free LDS pages, from
+ * the lowest round with sectors left, or from the next three rounds when none
+ * of that one fits, so the next batch's sectors start as soon as pages free
+ * up.  Every output of every round is the same as a separate
+ * afps_plan_launch of that round gives.
  *   rounds    DEVICE array of `count` afps_round entries, 1 <= count <= 4096
- *   workspace DEVICE, >= afps_plan_rounds_workspace_bytes(plan, count), the
- *             plan's tables uploaded into it (afps_plan_upload); the queue
- *             counters of every round follow the plan's own workspace
+ *   workspace DEVICE, >= afps_plan_rounds_workspace_bytes(plan, count) (the
+ *             plan's own workspace size: the claim counters of the rounds
+ *             live in LDS), the plan's tables uploaded into it (afps_plan_upload)
  * Only for plans whose sectors all use NPDU (AFPS_ERR_UNSUPPORTED otherwise)
  * and not with input checking on (each round's clouds are unknown to the
  * host).  Kernel launches only (capturable); asynchronous on `stream`.
@@ -266,7 +270,7 @@ int32_t afps_wall_clock_khz(void);
  * library holds on each GPU it runs on until the process ends, so the call
  * allocates nothing (no hipMalloc, hipFree or allocating library routine).
  * It copies the plan's tables into that array on `stream` and launches the
- * same kernels as afps_plan_launch, whose reset kernel clears the queue
+ * same kernels as afps_plan_launch, whose reset kernel clears the launch
  * counters first.  Every call on a GPU shares that GPU's array, which keeps
  * the last call's contents: calls that overlap on one GPU (several streams
  * or threads, or with a plan launched this way still running) race on it and
@@ -330,12 +334,17 @@ void afps_tune_reset(void);   /* forgets every tuned entry and the pool policy (
  * NPDU placement in batch plans created afterwards: NPDU sectors of at most
  * n_s_max points with windows k <= k_max keep their coordinates in LDS
  * (xyz_in_lds = 1: 16-byte records {D, x, y, z}, possible up to 8192 points)
- * or read them from L2 (0: only the distances take LDS, 4 bytes per point, so
- * a pooled CU holds four times the sectors).  The entry with the smallest
- * n_s_max (then k_max) that covers a sector decides; without one, sectors up
- * to 8192 points keep their coordinates in LDS.  Read from AFPS_TUNE_CACHE
- * as lines "npdu n_s_max k_max xyz_in_lds".  AFPS_ERR_ARG for bad values.
- * afps_npdu_xyz_in_lds reports the placement a sector would get.
+ * or out of LDS (0: only the distances take LDS, 4 bytes per point, so a
+ * pooled CU holds four times the sectors; the coordinates sit in vector
+ * registers for sectors of at most 4096 points with k <= 64 in pooled
+ * launches of at most 8 waves per workgroup, else they are read from L2).
+ * The entry with the smallest n_s_max (then k_max) that covers a sector
+ * decides; without one, sectors of at most 4096 points with k <= 64 hold
+ * their coordinates in registers (LDS when the pool policy asks for 12 or 16
+ * waves) and other sectors up to 8192 points in LDS.  Read from
+ * AFPS_TUNE_CACHE as lines "npdu n_s_max k_max xyz_in_lds".  AFPS_ERR_ARG
+ * for bad values.  afps_npdu_xyz_in_lds reports the placement a sector would
+ * get.
  */
 int afps_tune_npdu(int32_t n_s_max, int32_t k_max, int32_t xyz_in_lds);
 int afps_npdu_xyz_in_lds(int32_t n_s, int32_t k);
@@ -389,7 +398,8 @@ int afps_set_plan_occupancy(float waves_per_simd);
  * of the multi-workgroup plain-FPS kernel, or the page-allocation lock and
  * free pages of the pooled NPDU kernel.  A wait that exceeds it fails the
  * launch: the grid kernel's workgroups all return with -1 in the unfinished
- * outputs; a pooled wave marks every sector still queued -1.  Either records
+ * outputs; a pooled workgroup stops taking sectors and its last wave marks
+ * every sector of it no wave took -1 (in every round).  Either records
  * AFPS_ERR_DEVICE (afps_device_status, afps_plan_status).  Process-wide.
  */
 int afps_set_spin_limit(uint32_t polls);

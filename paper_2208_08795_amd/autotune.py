@@ -15,9 +15,9 @@ For the pooled NPDU launch of batch plans (one wave per sector, sectors
 placed into each CU's LDS pages), ``tune_npdu`` times the caller's own batch
 as it runs (one launch of several rounds) under each launch shape (waves per
 workgroup and workgroups per CU: the sector-to-CU mapping), each placement of
-the sectors' coordinates (LDS records, or L2 for the smaller sectors, which
-take a quarter of the pages) and each seeding policy, and installs the
-fastest.  Results can be written to a cache file that the library reads at
+the sectors' coordinates (registers up to some sector size, which leaves a
+quarter of the pages per sector, LDS records above) and each seeding policy,
+and installs the fastest.  Results can be written to a cache file that the library reads at
 first use (AFPS_TUNE_CACHE).
 """
 from __future__ import annotations
@@ -144,19 +144,21 @@ def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.0, 1.0, 2.0, 4
 
 
 # Pooled launch shapes (waves per workgroup, workgroups per CU) and coordinate
-# placements (sectors of at most n points read their coordinates from L2; 0 =
-# every sector keeps them in LDS) that tune_npdu tries.
-POOL_SHAPES = ((4, 1), (8, 1), (4, 2), (12, 1), (16, 1))
-L2_UP_TO = (0, 1024, 2048, 8192)
+# placements (sectors of at most n points hold their coordinates out of LDS:
+# in registers where the kernel can, else L2; larger ones in LDS records; 0 =
+# every sector in LDS) that tune_npdu tries.
+POOL_SHAPES = ((8, 1), (4, 1), (4, 2), (12, 1), (16, 1))
+REGS_UP_TO = (4096, 2048, 1024, 0)
 SEEDING = ((True, 3), (False, 3), (True, 0), (False, 0))
 
 
-def _apply_npdu(shape, l2_up_to, seeding, k_max):
+def _apply_npdu(shape, regs_up_to, seeding, k_max):
     from . import binding
     binding.tune_npdu_clear()
     binding.set_pool_policy(shape[0], shape[1], seeding[0], seeding[1])
-    if l2_up_to:
-        binding.tune_npdu(l2_up_to, k_max, False)
+    if regs_up_to:
+        binding.tune_npdu(regs_up_to, k_max, False)
+    binding.tune_npdu(8192, k_max, True)
 
 
 def tune_npdu(xyz_all, sizes, cs, ms, ks, starts, rounds: int = 20, reps: int = 3, install: bool = True,
@@ -166,7 +168,7 @@ def tune_npdu(xyz_all, sizes, cs, ms, ks, starts, rounds: int = 20, reps: int = 
     coordinate placement, then every seeding policy at the best of those; keep
     the fastest (installed in the library, optionally written to cache_path
     as "pool" and "npdu" lines).  Outputs of every configuration are checked
-    equal to the first one's.  Returns {"rows": [(shape, l2_up_to, seeding,
+    equal to the first one's.  Returns {"rows": [(shape, regs_up_to, seeding,
     ms per round)], "best": (...), "seconds": s}."""
     import torch
 
@@ -176,9 +178,9 @@ def tune_npdu(xyz_all, sizes, cs, ms, ks, starts, rounds: int = 20, reps: int = 
     k_max = max(k for k in ks if k is not None)
     rows, ref = [], None
 
-    def measure(shape, l2, seeding):
+    def measure(shape, regs, seeding):
         nonlocal ref
-        _apply_npdu(shape, l2, seeding, k_max)
+        _apply_npdu(shape, regs, seeding, k_max)
         plan = binding.BatchPlan(sizes, cs, ms, ks, starts, device=dev)
         if (plan.pool_waves, plan.pool_groups) != shape:   # the shape does not fit these sectors
             plan.close()
@@ -198,17 +200,17 @@ def tune_npdu(xyz_all, sizes, cs, ms, ks, starts, rounds: int = 20, reps: int = 
         if ref is None:
             ref = outs[0].clone()
         if not (torch.equal(outs[0], ref) and torch.equal(outs[1], ref)):
-            raise RuntimeError("tuned NPDU configuration %s/%s/%s changed the indices" % (shape, l2, seeding))
+            raise RuntimeError("tuned NPDU configuration %s/%s/%s changed the indices" % (shape, regs, seeding))
         plan.close()
         ms_ = float(np.median(ts))
-        rows.append((shape, l2, seeding, ms_))
+        rows.append((shape, regs, seeding, ms_))
         if log:
-            log("npdu tune: shape %s, L2 up to %d points, seeding %s: %.4f ms per batch" % (shape, l2, seeding, ms_))
+            log("npdu tune: shape %s, registers up to %d points, seeding %s: %.4f ms per batch" % (shape, regs, seeding, ms_))
         return ms_
 
     for shape in POOL_SHAPES:
-        for l2 in L2_UP_TO:
-            measure(shape, l2, SEEDING[0])
+        for regs in REGS_UP_TO:
+            measure(shape, regs, SEEDING[0])
     best = min(rows, key=lambda r: r[3])
     for seeding in SEEDING[1:]:
         measure(best[0], best[1], seeding)
@@ -222,4 +224,5 @@ def tune_npdu(xyz_all, sizes, cs, ms, ks, starts, rounds: int = 20, reps: int = 
             f.write("pool %d %d %d %d\n" % (best[0][0], best[0][1], int(best[2][0]), best[2][1]))
             if best[1]:
                 f.write("npdu %d %d 0\n" % (best[1], k_max))
+            f.write("npdu 8192 %d 1\n" % k_max)
     return {"rows": rows, "best": best, "seconds": time.perf_counter() - t0}

@@ -200,7 +200,7 @@ constexpr size_t kScratchBytes = size_t(1) << 20;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 constexpr int kHelperStreams = 4;
-constexpr int kMaxRounds = 4096;   // rounds of one pooled launch (2 MiB of queue counters)
+constexpr int kMaxRounds = 4096;   // rounds of one pooled launch
 constexpr int kGridBlocks = 16;
 
 // The barrier blocks of the multi-workgroup plain-FPS kernel and the
@@ -259,12 +259,12 @@ int device_state(DeviceState** out) {
         AFPS_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         d.cu_count = cus;
         d.max_lds = (size_t)lds;
-        // The pool takes a CU's whole LDS, less the kernel's static header.
+        // The pool takes a CU's whole LDS, less the kernel's static LDS.
         int per_cu = 0;
         if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
             per_cu <= 0)
             per_cu = lds;
-        d.pool_pages = std::min(kMaxPoolPages, (per_cu - 256) / kPoolPageBytes);
+        d.pool_pages = std::min(kMaxPoolPages, (per_cu - kPoolStaticLdsBytes) / kPoolPageBytes);
         // Kernels that take more than the default dynamic LDS.
         for (const auto& v : registry().full)
             if (v.lds_bytes > 0) {
@@ -736,7 +736,8 @@ struct afps_plan {
     std::vector<WorkItem> items;
     std::vector<PlannedBucket> buckets;
     std::vector<const void*> kernels;  // the kernel of each bucket
-    std::vector<PoolQueue> queues;    // pool queues, highest priority first
+    std::vector<PoolGroup> groups;    // each pooled workgroup's queues
+    std::vector<PoolQueue> queues;    // every pooled workgroup's queues, highest priority first
     std::vector<PoolSeed> seeds;      // first sector of each pool wave (workgroup-major)
     std::vector<CheckSeg> clouds;     // each descriptor's points, for the optional input check
     int pool_pages = 0;               // LDS pages of one pooled workgroup
@@ -801,6 +802,7 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     if ((rc = build_plan(descs, batch, env, &t, &err))) return fail(rc, err);
     plan->items = std::move(t.items);
     plan->buckets = std::move(t.buckets);
+    plan->groups = std::move(t.groups);
     plan->queues = std::move(t.queues);
     plan->seeds = std::move(t.seeds);
     plan->clouds = std::move(t.clouds);
@@ -853,12 +855,17 @@ void afps_plan_destroy(afps_plan* plan) { delete plan; }
 
 namespace {
 
-// Copy the plan's tables (pool queues, seeds, work items) into a workspace.
-// Pageable sources: the copies have consumed the host tables when this returns.
+// Copy the plan's tables (pool groups, queues and seeds, work items) into a
+// workspace.  Pageable sources: the copies have consumed the host tables when
+// this returns.
 int upload_tables(const afps_plan* plan, void* workspace, hipStream_t stream) {
+    if (!plan->groups.empty())
+        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolGroupOffset, plan->groups.data(),
+                                plan->groups.size() * sizeof(PoolGroup), hipMemcpyHostToDevice, stream));
     if (!plan->queues.empty())
-        AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolTableOffset, plan->queues.data(),
-                                plan->queues.size() * sizeof(PoolQueue), hipMemcpyHostToDevice, stream));
+        AFPS_HIP(hipMemcpyAsync((char*)workspace + pool_queue_offset((int64_t)plan->items.size()),
+                                plan->queues.data(), plan->queues.size() * sizeof(PoolQueue),
+                                hipMemcpyHostToDevice, stream));
     if (!plan->seeds.empty())
         AFPS_HIP(hipMemcpyAsync((char*)workspace + kPoolSeedOffset, plan->seeds.data(),
                                 plan->seeds.size() * sizeof(PoolSeed), hipMemcpyHostToDevice, stream));
@@ -901,7 +908,7 @@ int reset_words(unsigned* words, int count, hipStream_t stream) {
 // afps_plan_launch after argument checks: launches only (capturable).
 // `stamps`: per-item timestamps of the pooled NPDU launch, or nullptr.
 // `rounds`/`nrounds`: a launch of several rounds (pooled plans only): per-round
-// inputs and outputs (DEVICE), queue counters after the work items.
+// inputs and outputs (DEVICE).
 int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
                      hipStream_t stream, SectorStamp* stamps = nullptr, const PoolRound* rounds = nullptr,
                      int nrounds = 1) {
@@ -909,16 +916,12 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
     int rc = device_state(&d);
     if (rc) return rc;
     unsigned* counters = (unsigned*)workspace;
-    unsigned* qtaken = (unsigned*)((char*)workspace + kPoolCounterOffset);
-    const PoolQueue* queues = (const PoolQueue*)((char*)workspace + kPoolTableOffset);
+    const PoolGroup* groups = (const PoolGroup*)((char*)workspace + kPoolGroupOffset);
+    const PoolQueue* queues = (const PoolQueue*)((char*)workspace + pool_queue_offset((int64_t)plan->items.size()));
     const PoolSeed* seeds = (const PoolSeed*)((char*)workspace + kPoolSeedOffset);
     const WorkItem* items = (const WorkItem*)((char*)workspace + kItemsOffset);
     int nb = (int)plan->buckets.size();
     if ((rc = reset_words(counters, kResetWords, stream))) return rc;
-    if (rounds) {
-        qtaken = (unsigned*)((char*)workspace + plan->ws_bytes);
-        if ((rc = reset_words(qtaken, nrounds * kRoundCounters, stream))) return rc;
-    }
 
     auto launch_bucket = [&](int b, hipStream_t s) -> int {
         const PlannedBucket& bk = plan->buckets[b];
@@ -930,14 +933,12 @@ int plan_launch_impl(const afps_plan* plan, const float* xyz_all, int32_t* out_a
             pa.rounds = rounds;
             pa.nrounds = nrounds;
             pa.items = items;
+            pa.groups = groups;
             pa.queues = queues;
-            pa.qtaken = qtaken;
             pa.seeds = seeds;
             pa.status = counters + kStatusWord;
             pa.dev_status = d->status;
             pa.stamps = stamps;
-            pa.nq = (int)plan->queues.size();
-            pa.seed_groups = (int)plan->seeds.size() / (bk.block / 64);
             pa.pool_pages = plan->pool_pages;
             pa.spin_limit = g_spin_limit;
             pa.seed_priority = plan->seed_priority;
@@ -1052,7 +1053,14 @@ int afps_plan_launch_noalloc(const afps_plan* plan, const float* xyz_all, int32_
 }
 
 int32_t afps_noalloc_max_items(void) {
-    return (int32_t)((kScratchBytes - kItemsOffset) / sizeof(WorkItem));
+    // the largest count whose workspace (a queue per item at most) fits the scratch
+    int32_t lo = 0, hi = (int32_t)(kScratchBytes / sizeof(WorkItem));
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (workspace_bytes_for_items(mid) <= kScratchBytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 int afps_plan_launch_stamped(const afps_plan* plan, const float* xyz_all, int32_t* out_all, void* workspace,
@@ -1069,7 +1077,7 @@ int afps_plan_launch_stamped(const afps_plan* plan, const float* xyz_all, int32_
 
 size_t afps_plan_rounds_workspace_bytes(const afps_plan* plan, int32_t rounds) {
     if (!plan || plan->items.empty() || rounds < 1 || rounds > kMaxRounds) return 0;
-    return plan->ws_bytes + round_counters_bytes(rounds);
+    return plan->ws_bytes;   // the claim counters of a pooled launch live in LDS
 }
 
 int afps_plan_launch_rounds(const afps_plan* plan, const afps_round* rounds, int32_t count, void* workspace,

@@ -96,25 +96,32 @@ __device__ __forceinline__ T* global_ptr(int64_t bits) {
     return (T*)(__attribute__((address_space(1))) T*)bits;
 }
 
-// Pages a work item's sector occupies (its coordinates in LDS or not).
-__device__ __forceinline__ int item_pages(const WorkItem& wi) {
-    return npdu_pool_pages(wi.n, npdu_item_xyz_in_lds(wi.n, wi.flags));
-}
-
 // Sample one sector with the NPDU variant its size and coordinate placement
 // call for; `lds` is the first of its pages; LR points per lane in flight
-// while the sector loads.
-template <int LR>
+// while the sector loads.  Coordinates kept out of LDS live in registers
+// (REGS: kernels of at most two waves per SIMD, sectors of at most 4096
+// points, k <= 64), else they are read from L2.
+template <int LR, bool REGS>
 __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int32_t* __restrict__ out_all,
                                          const WorkItem& wi, uint32_t* lds, uint64_t* t_loaded) {
     const float* xyz = xyz_all + 3 * wi.xyz_offset;
     int32_t* out = out_all + wi.out_offset;
-    const int f = wi.flags & ~kItemXyzInL2;
+    const int f = wi.flags & ~kItemXyzNotInLds;
     const bool in_lds = npdu_item_xyz_in_lds(wi.n, wi.flags);
     switch (npdu_r_for(wi.n)) {
         case 1:
-            if (in_lds) sample_sector_npdu<1, true, LR>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
-            else sample_sector_npdu<1, false, LR>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
+            if (in_lds) {
+                sample_sector_npdu<1, true, LR>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
+            } else if (REGS && wi.k <= 64) {
+                if (f & kNpduShiftEdges)
+                    sample_sector_npdu_regs<true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
+                                                  (f & kNpduFirstFull) != 0, t_loaded);
+                else
+                    sample_sector_npdu_regs<false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
+                                                   (f & kNpduFirstFull) != 0, t_loaded);
+            } else {
+                sample_sector_npdu<1, false, LR>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
+            }
             break;
         case 2:
             if (in_lds) sample_sector_npdu<2, true, LR>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
@@ -127,64 +134,76 @@ __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int3
 
 }  // namespace
 
-// Rounds past a wave's lowest round with queued sectors that it may take
-// sectors from when none of that round fits its pool.
-constexpr int kRoundLookahead = 2;
-
+// The pooled NPDU kernel: one persistent workgroup of W waves per CU (or two
+// of four), every wave one sector at a time.  The plan gave each workgroup
+// its own sectors (the same for every round) in queues by page count; a
+// wave claims the next one under the workgroup's lock, entirely in LDS (the
+// claim counters of kRoundRing rounds at once and the page mask), so no
+// device-wide atomic is touched per sector: on MI355X those cross the XCDs.
 template <int W>
 __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
     static_assert(W <= kMaxPoolWaves, "seed table holds kMaxPoolWaves waves per workgroup");
+    static_assert(kMaxLocalQueues == 64, "one queue per lane");
     extern __shared__ __attribute__((aligned(16))) uint32_t pool[];
-    __shared__ uint64_t used[3];
+    __shared__ uint64_t used[3];                              // page mask, bit set = in use
     __shared__ uint32_t lock;
+    __shared__ uint32_t taken[kRoundRing][kMaxLocalQueues];   // claims per queue of round r in slot r % kRoundRing
+    __shared__ int32_t low;                                   // rounds below have every sector claimed
+    __shared__ uint32_t exited;                               // waves that left the work loop
+    __shared__ uint32_t gave_up;                              // a wave of this workgroup gave up a bounded wait
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int nq = a.nq;
     const int nrounds = a.nrounds;
     const unsigned spin_limit = a.spin_limit;
     const WorkItem* __restrict__ items = a.items;
-    const PoolQueue* __restrict__ queues = a.queues;
-    const bool seeded = (int)blockIdx.x < a.seed_groups;
+    const PoolGroup grp = a.groups[blockIdx.x];
+    // This lane's queue: first item, items per round (round 0 without the
+    // seeded ones), pages; lanes past the workgroup's queues hold none.
+    PoolQueue Q{0, 0, 0x7FFFFFFF, 0};
+    if (lane < grp.queues) Q = a.queues[grp.queue_first + lane];
+    const PoolSeed* seeds = a.seeds + (size_t)blockIdx.x * W;
     if (threadIdx.x < 3) {
         const int wd = (int)threadIdx.x, lo = 64 * wd;
         uint64_t u = a.pool_pages <= lo ? ~0ull : (a.pool_pages >= lo + 64 ? 0ull : (~0ull << (a.pool_pages - lo)));
-        if (seeded)
-            for (int w = 0; w < W; ++w) {
-                const PoolSeed sd = a.seeds[blockIdx.x * W + w];
-                if (sd.item >= 0) u |= page_bits(wd, sd.page, item_pages(items[sd.item]));
-            }
+        for (int w = 0; w < W; ++w) {
+            const PoolSeed sd = seeds[w];
+            if (sd.item >= 0) u |= page_bits(wd, sd.page, sd.pages);
+        }
         used[wd] = u;
     }
-    if (threadIdx.x == 0) lock = 0u;
+    for (int i = threadIdx.x; i < kRoundRing * kMaxLocalQueues; i += 64 * W) (&taken[0][0])[i] = 0u;
+    if (threadIdx.x == 0) {
+        lock = 0u;
+        low = 0;
+        exited = 0u;
+        gave_up = 0u;
+    }
     __syncthreads();   // the only workgroup barrier: from here on waves are independent
 
-    // This lane's two queues (lane, lane + 64): page counts, items per round
-    // (round 0 without the seeded ones) and their first items.
-    const int q0 = lane, q1 = lane + 64;
-    PoolQueue Q0{0, 0, 0x7FFFFFFF, 0}, Q1{0, 0, 0x7FFFFFFF, 0};
-    if (q0 < nq) Q0 = queues[q0];
-    if (q1 < nq) Q1 = queues[q1];
-
     // The sector in hand: the wave's seed first (round 0, pages marked
-    // before the barrier), then whatever the queues hand out.
-    int item = -1, page = 0, pages = 0, round = 0, sleeps = 0;
+    // before the barrier), then whatever the workgroup's queues hand out.
+    int item = -1, page = 0, pages = 0, sleeps = 0;
     bool first_seed = false;
-    if (seeded) {
-        const PoolSeed sd = a.seeds[blockIdx.x * W + wv];
+    WorkItem wi{};
+    PoolRound rp{a.xyz_all, a.out_all};
+    {
+        const PoolSeed sd = seeds[wv];
         if (sd.item >= 0) {
             item = sd.item;
             page = sd.page;
-            pages = item_pages(items[item]);
+            pages = sd.pages;
             sleeps = sd.sleeps;
             first_seed = true;
+            wi = items[item];
+            if (a.rounds) rp = a.rounds[0];
         }
     }
-    int low = 0;   // lowest round that may still have queued sectors
     unsigned spins = 0;
     bool failed = false;
     for (;;) {
         if (item < 0) {
-            // ---- take the allocation lock (lane 0 polls; the wave follows)
+            if (__hip_atomic_load(&gave_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+            // ---- the workgroup lock (lane 0 polls; the wave follows)
             int got = 0;
             if (lane == 0) {
                 for (;;) {
@@ -203,8 +222,11 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
                 failed = true;
                 break;
             }
-
-            // ---- largest free run of pages, per start page (three per lane)
+            // ---- under the lock: the longest free run of pages, then the
+            // first queue (highest priority) with sectors left that fits it, in
+            // the lowest round with sectors left, else up to kRoundRing - 1
+            // rounds further.  Rounds at the front with every sector claimed
+            // pass their counter slot on to round r + kRoundRing.
             const uint64_t u0 = __hip_atomic_load(&used[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             const uint64_t u1 = __hip_atomic_load(&used[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             const uint64_t u2 = __hip_atomic_load(&used[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -212,78 +234,78 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
             const int r1 = free_run(1, lane, u0, u1, u2);
             const int r2 = free_run(2, lane, u0, u1, u2);
             const int longest = (int)wave_max((uint32_t)max(r0, max(r1, r2)));
-
-            // ---- the first queue (highest priority) with sectors left that
-            // fits, in the lowest round with sectors left, else up to
-            // kRoundLookahead rounds further
+            const int lw = __builtin_amdgcn_readfirstlane(__hip_atomic_load(&low, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            int lw_new = lw;
             int q = -1, qr = 0;
-            for (int r = low; r < nrounds && r < low + kRoundLookahead; r = __builtin_amdgcn_readfirstlane(r + 1)) {
-                unsigned* ctr = a.qtaken + (size_t)r * kRoundCounters;
-                const int avail0 = r == 0 ? Q0.count - Q0.seeded : Q0.count;
-                const int avail1 = r == 0 ? Q1.count - Q1.seeded : Q1.count;
-                const unsigned t0 = q0 < nq ? __hip_atomic_load(&ctr[q0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-                const unsigned t1 = q1 < nq ? __hip_atomic_load(&ctr[q1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-                const bool left0 = t0 < (unsigned)avail0, left1 = t1 < (unsigned)avail1;
-                if ((ballot(left0) | ballot(left1)) == 0ull) {   // round r is drained for good
-                    if (r == low) low = r + 1;
-                    continue;
+            unsigned idx = 0u;
+            bool front = true;
+#pragma unroll
+            for (int i = 0; i < kRoundRing; ++i) {
+                const int r = lw + i;
+                if (q < 0 && r < nrounds) {
+                    uint32_t* const slot = taken[r & (kRoundRing - 1)];
+                    const uint32_t t = __hip_atomic_load(&slot[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const int avail = r == 0 ? Q.count - Q.seeded : Q.count;
+                    const uint64_t left = ballot(t < (uint32_t)avail);
+                    if (left == 0ull) {
+                        if (front) {   // round r is claimed for good: the slot is round r + kRoundRing's
+                            __hip_atomic_store(&slot[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            lw_new = r + 1;
+                        }
+                    } else {
+                        front = false;
+                        const uint64_t fit = left & ballot(Q.pages <= longest);
+                        if (fit) {
+                            q = (int)__builtin_ctzll(fit);
+                            qr = r;
+                            idx = (uint32_t)__builtin_amdgcn_readlane((int)t, q);
+                            if (lane == q)
+                                __hip_atomic_store(&slot[lane], t + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
                 }
-                const uint64_t fit0 = ballot(left0 && Q0.pages <= longest), fit1 = ballot(left1 && Q1.pages <= longest);
-                if (fit0 | fit1) {
-                    q = fit0 ? (int)__builtin_ctzll(fit0) : 64 + (int)__builtin_ctzll(fit1);
-                    qr = r;
+            }
+            if (lw_new != lw && lane == 0) __hip_atomic_store(&low, lw_new, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (q < 0) {
+                if (lane == 0) __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (lw_new >= nrounds) break;   // every sector of every round is claimed
+                // Nothing left fits the free pages now (they are held by
+                // other waves of this workgroup): poll again.
+                if (++spins >= spin_limit) {
+                    failed = true;
                     break;
                 }
-            }
-            if (low >= nrounds) {   // every round is drained
-                if (lane == 0) __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                break;
-            }
-            if (q >= 0) {
-                unsigned idx = 0;
-                if (lane == 0) idx = atomicAdd(&a.qtaken[(size_t)qr * kRoundCounters + q], 1u);
-                idx = (unsigned)__builtin_amdgcn_readfirstlane((int)idx);
-                const PoolQueue Q = queues[q];
-                const int skip = qr == 0 ? Q.seeded : 0;
-                if (idx < (unsigned)(Q.count - skip)) {
-                    item = Q.first + skip + (int)idx;
-                    pages = Q.pages;
-                    round = qr;
-                }
-            }
-            if (item < 0) {
-                // Nothing fits now (pages held by other waves of this workgroup),
-                // or the queue emptied meanwhile: release and poll again.
-                if (lane == 0) __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (q < 0) {
-                    if (++spins >= spin_limit) {
-                        failed = true;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
+                __builtin_amdgcn_s_sleep(2);
                 continue;
             }
-
-            // ---- first fit of the item's pages, marked used, lock released
-            const uint64_t b0 = ballot(r0 >= pages), b1 = ballot(r1 >= pages), b2 = ballot(r2 >= pages);
+            // ---- the first fit of the queue's pages, marked used; lock released
+            q = __builtin_amdgcn_readfirstlane(q);
+            qr = __builtin_amdgcn_readfirstlane(qr);
+            const int q_pages = __builtin_amdgcn_readlane(Q.pages, q);
+            const uint64_t b0 = ballot(r0 >= q_pages), b1 = ballot(r1 >= q_pages), b2 = ballot(r2 >= q_pages);
             page = b0 ? (int)__builtin_ctzll(b0) : (b1 ? 64 + (int)__builtin_ctzll(b1) : 128 + (int)__builtin_ctzll(b2));
-            const uint64_t m0 = page_bits(0, page, pages), m1 = page_bits(1, page, pages), m2 = page_bits(2, page, pages);
+            const uint64_t m0 = page_bits(0, page, q_pages), m1 = page_bits(1, page, q_pages),
+                           m2 = page_bits(2, page, q_pages);
             if (lane == 0) {
                 if (m0) __hip_atomic_fetch_or(&used[0], m0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (m1) __hip_atomic_fetch_or(&used[1], m1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (m2) __hip_atomic_fetch_or(&used[2], m2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 __hip_atomic_store(&lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // the previous owner's accesses are done
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // the pages' previous owner is done with them
             spins = 0;                                                // the limit bounds each wait
+            const int skip = qr == 0 ? __builtin_amdgcn_readlane(Q.seeded, q) : 0;
+            item = __builtin_amdgcn_readlane(Q.first, q) + skip + (int)idx;
+            pages = q_pages;
+            wi = items[item];
+            if (a.rounds) rp = a.rounds[qr];
         }
 
         // ---- sample the sector in hand (the one call site of the samplers)
         for (int z = 0; z < sleeps; ++z) __builtin_amdgcn_s_sleep(127);   // kSeedSleepCycles each
-        // Wave 0's seed is its workgroup's longest sector (the first round of
-        // seeds takes the longest sectors): with a seed priority, its
-        // instructions go first when a SIMD has another wave ready too.
+        // Wave 0's seed is its workgroup's longest sector (the seeds take
+        // the longest sectors first): with a seed priority, its instructions
+        // go first when a SIMD has another wave ready too.
         const bool raise = first_seed && wv == 0 && a.seed_priority > 0;
         if (raise) {
             switch (a.seed_priority) {
@@ -297,16 +319,13 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
         // around the allocation it cannot prove it).
         item = __builtin_amdgcn_readfirstlane(item);
         page = __builtin_amdgcn_readfirstlane(page);
-        round = __builtin_amdgcn_readfirstlane(round);
-        const WorkItem wi = uniform_item(items[item]);
-        const float* xyz_r = global_ptr<const float>(
-            uniform64(reinterpret_cast<int64_t>(a.rounds ? a.rounds[round].xyz_all : a.xyz_all)));
-        int32_t* out_r = global_ptr<int32_t>(
-            uniform64(reinterpret_cast<int64_t>(a.rounds ? a.rounds[round].out_all : a.out_all)));
+        const WorkItem wu = uniform_item(wi);
+        const float* xyz_r = global_ptr<const float>(uniform64(reinterpret_cast<int64_t>(rp.xyz_all)));
+        int32_t* out_r = global_ptr<int32_t>(uniform64(reinterpret_cast<int64_t>(rp.out_all)));
         const uint64_t take_rt = __builtin_amdgcn_s_memrealtime();
         const uint64_t take = __builtin_amdgcn_s_memtime();
         uint64_t loaded = take;
-        run_item<(W > 8 ? 16 : kLoadRound)>(xyz_r, out_r, wi, pool + page * (kPoolPageBytes / 4), &loaded);
+        run_item<(W > 8 ? 16 : kLoadRound), (W <= 8)>(xyz_r, out_r, wu, pool + page * (kPoolPageBytes / 4), &loaded);
         if (a.stamps) {
             const uint64_t end = __builtin_amdgcn_s_memtime();
             const uint64_t end_rt = __builtin_amdgcn_s_memrealtime();
@@ -318,9 +337,9 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
                 st.take_rt = take_rt;
                 st.end_rt = end_rt;
                 st.item = item;
-                st.n = wi.n;
-                st.c = wi.c;
-                st.k = wi.k;
+                st.n = wu.n;
+                st.c = wu.c;
+                st.k = wu.k;
                 // HW_ID (register 4) and XCC_ID (register 20), whole 32-bit registers
                 st.hw_id = (uint32_t)__builtin_amdgcn_s_getreg((31 << 11) | 4);
                 st.xcc_id = (uint32_t)__builtin_amdgcn_s_getreg((31 << 11) | 20);
@@ -337,26 +356,35 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
         item = -1;
         sleeps = 0;
         first_seed = false;
+        // not carried past the sampler in registers: set again by the next claim
+        wi = WorkItem{};
+        rp = PoolRound{a.xyz_all, a.out_all};
     }
-    if (!failed) return;
-    // Gave up waiting: report it, take every sector still queued in any round
-    // and mark it failed.
-    if (lane == 0) {
+
+    // ---- leaving.  A wave that gave up reports it and stops the workgroup
+    // claiming; the last wave out then marks every sector no wave claimed
+    // failed (every claimed sector ran to its end).
+    if (failed && lane == 0) {
+        __hip_atomic_fetch_or(&gave_up, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_or(a.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_or(a.dev_status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    for (int r = 0; r < nrounds; ++r) {
-        int32_t* out_r = a.rounds ? a.rounds[r].out_all : a.out_all;
-        for (int q = 0; q < nq; ++q) {
-            const PoolQueue Q = queues[q];
-            const int skip = r == 0 ? Q.seeded : 0;
-            for (;;) {
-                unsigned idx = 0;
-                if (lane == 0) idx = atomicAdd(&a.qtaken[(size_t)r * kRoundCounters + q], 1u);
-                idx = (unsigned)__builtin_amdgcn_readfirstlane((int)idx);
-                if (idx >= (unsigned)(Q.count - skip)) break;
-                fail_item(items[Q.first + skip + (int)idx], out_r, lane);
-            }
+    unsigned before = 0u;
+    if (lane == 0) before = __hip_atomic_fetch_add(&exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    before = (unsigned)__builtin_amdgcn_readfirstlane((int)before);
+    if (before != (unsigned)(W - 1)) return;
+    if (!__hip_atomic_load(&gave_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
+    const int lw = __builtin_amdgcn_readfirstlane(__hip_atomic_load(&low, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    for (int r = lw; r < nrounds; ++r) {
+        int32_t* out_r = global_ptr<int32_t>(uniform64(reinterpret_cast<int64_t>(a.rounds ? a.rounds[r].out_all : a.out_all)));
+        const uint32_t t = r < lw + kRoundRing
+                               ? __hip_atomic_load(&taken[r & (kRoundRing - 1)][lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                               : 0u;
+        for (int q = 0; q < grp.queues; ++q) {
+            const int skip = r == 0 ? __builtin_amdgcn_readlane(Q.seeded, q) : 0;
+            const int first = __builtin_amdgcn_readlane(Q.first, q), count = __builtin_amdgcn_readlane(Q.count, q);
+            for (int i = first + skip + __builtin_amdgcn_readlane((int)t, q); i < first + count; ++i)
+                fail_item(uniform_item(items[i]), out_r, lane);
         }
     }
 }

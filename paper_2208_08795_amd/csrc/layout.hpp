@@ -22,9 +22,11 @@ constexpr int kNpduFirstFull = 1;
 constexpr int kNpduShiftEdges = 2;
 constexpr int kNpduKWithSelf = 4;
 // Work-item flag set by the planner (not a reading): the sector's coordinates
-// stay in global memory (L2) and only its distances take LDS, for a sector
-// small enough to hold its coordinates in LDS too.
-constexpr int kItemXyzInL2 = 1 << 8;
+// stay out of LDS, for a sector small enough to hold them in LDS too; only its
+// distances take LDS.  The pooled kernels of at most two waves per SIMD hold
+// such a sector's coordinates in registers when it has at most 4096 points and
+// k <= 64; otherwise they read them from global memory (L2).
+constexpr int kItemXyzNotInLds = 1 << 8;
 
 // One sector's work, as the batch queue hands it out (40 bytes).
 struct WorkItem {
@@ -35,7 +37,7 @@ struct WorkItem {
     int32_t k;            // NPDU window parameter, < 0 = off
     int32_t start;        // local start point (start mod n)
     int32_t base;         // index of the sector's first point inside its cloud
-    int32_t flags;        // NPDU readings (kNpdu*) and kItemXyzInL2; 0 without NPDU
+    int32_t flags;        // NPDU readings (kNpdu*) and kItemXyzNotInLds; 0 without NPDU
 };
 static_assert(sizeof(WorkItem) == 40, "work item layout");
 
@@ -55,14 +57,20 @@ constexpr int kMaxNpduLdsXyz = 8192;   // largest sector whose coordinates fit i
 // records of 16 bytes); a sector holds exactly npdu_pool_pages contiguous pages.
 constexpr int kPoolPageBytes = 1024;
 constexpr int kMaxPoolPages = 160;      // pages per workgroup, at most (used-mask of 3 words)
-constexpr int kMaxPoolQueues = 128;     // two per lane in the queue scan
 constexpr int kMaxPoolWaves = 16;
-constexpr int kMaxPoolSeedGroups = 512;
+constexpr int kMaxPoolGroups = 512;     // pooled workgroups of one launch, at most
+constexpr int kMaxLocalQueues = 64;     // queues of one pooled workgroup (one per lane)
+constexpr int kRoundRing = 4;           // rounds a pooled workgroup takes sectors from at once
+static_assert((kRoundRing & (kRoundRing - 1)) == 0, "ring slots by mask");
+// LDS the pooled kernel declares statically (page mask, lock, the claim
+// counters of kRoundRing rounds, round and exit words), bounded: the pool
+// takes the rest of the CU's LDS.
+constexpr int kPoolStaticLdsBytes = 2048;
 constexpr int kSeedSleepCycles = 127 * 64;   // one s_sleep(127)
 
 // Whether a pooled NPDU sector keeps its coordinates in LDS, from its item flags.
 constexpr bool npdu_item_xyz_in_lds(int n, int flags) {
-    return npdu_r_for(n) <= 2 && (flags & kItemXyzInL2) == 0;
+    return npdu_r_for(n) <= 2 && (flags & kItemXyzNotInLds) == 0;
 }
 constexpr int npdu_pool_pages(int n, bool xyz_in_lds) {
     return (4 * npdu_lds_words(n, xyz_in_lds) + kPoolPageBytes - 1) / kPoolPageBytes;
@@ -70,28 +78,39 @@ constexpr int npdu_pool_pages(int n, bool xyz_in_lds) {
 // Pages of the sector the built-in placement gives (coordinates in LDS up to 8192 points).
 constexpr int npdu_pool_pages(int n) { return npdu_pool_pages(n, npdu_r_for(n) <= 2); }
 
-// A queue of pooled sectors that all need the same pages, longest first:
-// items [first, first + count) of the plan, of which the first `seeded` are
-// the first sectors of waves in round 0 (they are not queued in that round).
+// A pooled launch assigns every sector to one workgroup when the plan is
+// built (balanced by estimated cost), for every round alike.  Inside a
+// workgroup its sectors are queued by the pages they take: a queue holds
+// items [first, first + count) of the plan, longest first, that all take
+// `pages` pages (at least what each needs); the first `seeded` are the first
+// sectors of the workgroup's waves in round 0 (not queued in that round).
 struct PoolQueue {
     int32_t first;
     int32_t count;
-    int32_t pages;     // pages every item of the queue needs
+    int32_t pages;
     int32_t seeded;
 };
-// Queue counters of one round of a pooled launch (one per queue).
-constexpr int kRoundCounters = 128;
 static_assert(sizeof(PoolQueue) == 16, "pool queue layout");
 
+// A pooled workgroup's queues: [queue_first, queue_first + queues) of the
+// plan's queue table, highest priority first, at most kMaxLocalQueues.
+struct PoolGroup {
+    int32_t queue_first;
+    int32_t queues;
+};
+static_assert(sizeof(PoolGroup) == 8, "pool group layout");
+
 // First sector of each pooled wave, assigned when the plan is built: the
-// item, its first page and how many sleep periods (kSeedSleepCycles each) the
-// wave waits before loading it; item -1 if none.
+// item, its first page, the pages it takes and how many sleep periods
+// (kSeedSleepCycles each) the wave waits before loading it; item -1 if none.
 struct PoolSeed {
     int32_t item;
     int16_t page;
-    int16_t sleeps;
+    uint8_t pages;
+    uint8_t sleeps;
 };
 static_assert(sizeof(PoolSeed) == 8, "pool seed layout");
+static_assert(kMaxPoolPages < 256, "seed pages in a byte");
 
 // One cloud's points, for the optional input check.
 struct CheckSeg {
@@ -101,25 +120,25 @@ struct CheckSeg {
 };
 
 // Device workspace of a batch plan:
-//   [bucket counters (63) | status word | pool queue counters (128) |
-//    pool queue table (128 x 16 B) | pool seeds (512 x 16 x 8 B) | work items]
+//   [bucket counters (63) | status word | pool groups (512 x 8 B) |
+//    pool seeds (512 x 16 x 8 B) | work items | pool queues (at most one per item)]
 constexpr size_t kCounterBytes = 256;
 constexpr int kStatusWord = (int)(kCounterBytes / sizeof(unsigned)) - 1;   // set by a wave that gave up
 constexpr int kMaxBuckets = kStatusWord;
-constexpr size_t kPoolCounterOffset = kCounterBytes;
-constexpr size_t kPoolTableOffset = kPoolCounterOffset + kMaxPoolQueues * sizeof(unsigned);
-constexpr size_t kPoolSeedOffset = kPoolTableOffset + kMaxPoolQueues * sizeof(PoolQueue);
-constexpr size_t kItemsOffset = kPoolSeedOffset + (size_t)kMaxPoolSeedGroups * kMaxPoolWaves * sizeof(PoolSeed);
+constexpr size_t kPoolGroupOffset = kCounterBytes;
+constexpr size_t kPoolSeedOffset = kPoolGroupOffset + (size_t)kMaxPoolGroups * sizeof(PoolGroup);
+constexpr size_t kItemsOffset = kPoolSeedOffset + (size_t)kMaxPoolGroups * kMaxPoolWaves * sizeof(PoolSeed);
 static_assert(kItemsOffset % 256 == 0, "work items start 256-byte aligned");
-constexpr int kResetWords = (int)(kPoolTableOffset / sizeof(unsigned));   // counters and status, cleared per launch
+constexpr int kResetWords = (int)(kCounterBytes / sizeof(unsigned));   // counters and status, cleared per launch
 
-constexpr size_t workspace_bytes_for_items(int64_t items) {
-    return items <= 0 ? 0 : ((kItemsOffset + (size_t)items * sizeof(WorkItem)) + 255) / 256 * 256;
+// The pool queue table follows the work items (16-byte aligned).
+constexpr size_t pool_queue_offset(int64_t items) {
+    return (kItemsOffset + (size_t)(items < 0 ? 0 : items) * sizeof(WorkItem) + 15) / 16 * 16;
 }
-// A launch of several rounds adds the queue counters of every round after
-// the work items.
-constexpr size_t round_counters_bytes(int64_t rounds) {
-    return rounds <= 0 ? 0 : ((size_t)rounds * kRoundCounters * sizeof(unsigned) + 255) / 256 * 256;
+// Workspace of a plan of `items` work items: room for a queue per item, the
+// most a plan can have.
+constexpr size_t workspace_bytes_for_items(int64_t items) {
+    return items <= 0 ? 0 : (pool_queue_offset(items) + (size_t)items * sizeof(PoolQueue) + 255) / 256 * 256;
 }
 
 }  // namespace afps

@@ -11,13 +11,15 @@ namespace afps {
 namespace {
 
 // Estimated cycles of one NPDU iteration of one wave (window within two
-// blocks), by block registers and coordinate placement: measured per-sector
-// cycles per iteration at 4096 / 8192 / 16 384 / 32 768 points; coordinates
-// from L2 cost an L2 round trip per iteration where LDS would serve.
-double npdu_iter_cycles(int n, bool xyz_in_lds) {
+// blocks) with another wave on its SIMD, by block registers and coordinate
+// placement: measured per-sector cycles per iteration of pooled launches.
+// Coordinates in registers (sectors of at most 4096 points, k <= 64) cost
+// the lane selects of the register sets; from L2 they cost a round trip per
+// iteration where LDS would serve.
+double npdu_iter_cycles(int n, bool xyz_in_lds, int k) {
     switch (npdu_r_for(n)) {
-        case 1: return xyz_in_lds ? 540.0 : 680.0;
-        case 2: return xyz_in_lds ? 650.0 : 760.0;
+        case 1: return xyz_in_lds ? 520.0 : (k <= 64 ? 640.0 : 1300.0);
+        case 2: return xyz_in_lds ? 650.0 : 1300.0;
         case 4: return 830.0;
         default: return 1000.0;
     }
@@ -85,7 +87,8 @@ bool npdu_xyz_in_lds(const PoolPolicy& policy, int n, int k) {
     if (npdu_r_for(n) > 2) return false;
     for (const auto& e : policy.placement)
         if (n <= e.n_max && k <= e.k_max) return e.xyz_in_lds != 0;
-    return true;
+    // built-in: registers for the sectors they serve best, else LDS
+    return !(n <= kRegsDefaultMaxPoints && k <= 64 && policy.waves <= 8);
 }
 
 int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& env, PlanTables* out,
@@ -139,11 +142,11 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
                     return AFPS_ERR_UNSUPPORTED;
                 }
                 const bool in_lds = npdu_xyz_in_lds(env.pool, ns, it.k);
-                if (!in_lds && npdu_r_for(ns) <= 2) it.flags |= kItemXyzInL2;
+                if (!in_lds && npdu_r_for(ns) <= 2) it.flags |= kItemXyzNotInLds;
                 st.full.id = -1;
                 st.pages = npdu_pool_pages(ns, in_lds);
                 // windows wider than two blocks re-reduce one more block pair per extra 128
-                st.cost = (double)cs * npdu_iter_cycles(ns, in_lds) * (1.0 + std::max(0, it.k - 64) / 128.0);
+                st.cost = (double)cs * npdu_iter_cycles(ns, in_lds, it.k) * (1.0 + std::max(0, it.k - 64) / 128.0);
             } else {
                 FullVariantInfo v{};
                 if (!env.choose_full || !env.choose_full(ns, &v)) {
@@ -164,30 +167,14 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
     }
     plan.pool_pages = env.cu_pool_pages;
 
-    // ---- NPDU sectors: one pooled launch.  Queues by page count, each
-    // longest first; queues ordered by their longest sector.
+    // ---- NPDU sectors: one pooled launch.
     std::vector<Staged> npdu, full;
     for (auto& st : staged) (st.full.id < 0 ? npdu : full).push_back(st);
-    std::stable_sort(npdu.begin(), npdu.end(), [](const Staged& a, const Staged& b) {
-        if (a.pages != b.pages) return a.pages > b.pages;
-        return a.cost > b.cost;
-    });
-    std::vector<std::pair<double, std::pair<int, int>>> qorder;   // (longest cost, [first, count))
-    for (size_t i = 0; i < npdu.size();) {
-        size_t j = i;
-        while (j < npdu.size() && npdu[j].pages == npdu[i].pages) ++j;
-        if (npdu[i].pages > plan.pool_pages) {
-            *err = "NPDU sector of " + std::to_string(npdu[i].item.n) + " points exceeds the LDS of one CU";
+    for (const auto& st : npdu)
+        if (st.pages > plan.pool_pages) {
+            *err = "NPDU sector of " + std::to_string(st.item.n) + " points exceeds the LDS of one CU";
             return AFPS_ERR_UNSUPPORTED;
         }
-        qorder.push_back({npdu[i].cost, {(int)i, (int)(j - i)}});
-        i = j;
-    }
-    if ((int)qorder.size() > kMaxPoolQueues) {
-        *err = "too many NPDU sector sizes";
-        return AFPS_ERR_UNSUPPORTED;
-    }
-    std::stable_sort(qorder.begin(), qorder.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
 
     // Full-update sectors: one bucket per (variant, LDS), longest first inside.
     std::stable_sort(full.begin(), full.end(), [](const Staged& a, const Staged& b) {
@@ -201,18 +188,13 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
     item_cost.reserve(staged.size());
     if (!npdu.empty()) {
         PlannedBucket bk{-1, 0, 0, 0, 0, 0, 0.0, 0.0};
-        for (const auto& q : qorder) {
-            const int first = (int)plan.items.size();
-            for (int i = 0; i < q.second.second; ++i) {
-                const Staged& st = npdu[q.second.first + i];
-                plan.items.push_back(st.item);
-                item_cost.push_back(st.cost);
-                bk.cost += st.cost;
-                bk.longest = std::max(bk.longest, st.cost);
-            }
-            plan.queues.push_back({first, q.second.second, npdu[q.second.first].pages, 0});   // seeded below
+        int max_pages = 0;
+        for (const auto& st : npdu) {
+            bk.cost += st.cost;
+            bk.longest = std::max(bk.longest, st.cost);
+            max_pages = std::max(max_pages, st.pages);
         }
-        bk.count = (int)plan.items.size();
+        bk.count = (int)npdu.size();
         // Waves per CU: one per SIMD keeps the longest sectors at full speed;
         // two per SIMD give more throughput (about 1.7x) when the batch is
         // bound by total work rather than by its longest sector.
@@ -226,8 +208,6 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
         // runs as fast either way, but a launch then gives its LDS back half
         // a CU at a time, so a launch queued behind it on another stream
         // starts sooner.
-        int max_pages = 0;
-        for (const auto& q : plan.queues) max_pages = std::max(max_pages, q.pages);
         plan.pool_groups = waves == 8 && max_pages <= plan.pool_pages / 2 ? 2 : 1;
         if (plan.pool_groups == 2) waves = 4;
         if (env.pool.waves > 0 && env.pool.groups > 0) {   // an explicit (tuned) shape
@@ -243,36 +223,104 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
         plan.seed_priority = std::max(0, std::min(3, env.pool.seed_priority));
         bk.block = 64 * waves;
         bk.lds_bytes = plan.pool_pages * kPoolPageBytes;
-        bk.grid = std::min(plan.pool_groups * env.cu_count, bk.count);
-        // Seeds: the queue policy of the kernel played out on the host for
-        // the moment every wave starts (wave w of every workgroup, then wave
-        // w + 1, each taking the first queue with sectors left that fits its
-        // workgroup's pages), so that a launch starts without a rush of every
-        // wave on the same queue counter.  A workgroup's seeds sit in
-        // consecutive pages from page 0; the seeded sectors are the front of
-        // their queues, which in round 0 start after them.  Seeds after the first
-        // round whose estimated cost leaves room before the plan's longest
-        // item wait one sleep period before loading: the first round (the
-        // longest sectors) then loads with less competition for bandwidth,
-        // and the wait cannot lengthen the launch by the cost model.
-        const int sg = std::min(bk.grid, kMaxPoolSeedGroups);
-        plan.seeds.assign((size_t)sg * waves, PoolSeed{-1, 0, 0});
-        std::vector<int> taken(plan.queues.size(), 0), used(sg, 0);
-        for (int w = 0; w < waves; ++w)
-            for (int g = 0; g < sg; ++g)
-                for (size_t q = 0; q < plan.queues.size(); ++q) {
-                    const PoolQueue& Q = plan.queues[q];
-                    if (taken[q] < Q.count && used[g] + Q.pages <= plan.pool_pages) {
-                        const int item = Q.first + taken[q];
+        const int G = std::min({plan.pool_groups * env.cu_count, bk.count, kMaxPoolGroups});
+        bk.grid = G;
+
+        // Every sector goes to one workgroup for good (and so for every
+        // round alike): longest-processing-time first, each to the workgroup
+        // that is least loaded, counting a workgroup's load as its estimated
+        // cycles over its waves or its page-weighted cycles over its pages,
+        // whichever is larger (large sectors run fewer at a time).  Claims
+        // then stay inside the workgroup's LDS: no device-wide counter is
+        // touched per sector.
+        std::vector<int> order(npdu.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return npdu[x].cost > npdu[y].cost; });
+        std::vector<double> load_c(G, 0.0), load_p(G, 0.0);
+        auto key = [&](int g) { return std::max(load_c[g] / waves, load_p[g] / plan.pool_pages); };
+        auto later = [&](int x, int y) { return key(x) > key(y) || (key(x) == key(y) && x > y); };
+        std::vector<int> heap(G);
+        for (int g = 0; g < G; ++g) heap[g] = g;
+        std::make_heap(heap.begin(), heap.end(), later);
+        std::vector<std::vector<int>> members(G);
+        for (int i : order) {
+            std::pop_heap(heap.begin(), heap.end(), later);
+            const int g = heap.back();
+            members[g].push_back(i);   // in descending cost
+            load_c[g] += npdu[i].cost;
+            load_p[g] += npdu[i].cost * npdu[i].pages;
+            std::push_heap(heap.begin(), heap.end(), later);
+        }
+
+        // Inside a workgroup: queues by pages (rounded up to fewer distinct
+        // counts if there would be more than kMaxLocalQueues), longest first,
+        // the queues ordered by their longest sector.  Seeds: the queue
+        // policy of the kernel played out for the moment every wave starts
+        // (wave 0 first, each taking the first queue with sectors left that
+        // fits the workgroup's pages), so that a launch starts without a rush
+        // on the workgroup's lock.  A workgroup's seeds sit in consecutive
+        // pages from page 0; the seeded sectors are the front of their queues,
+        // which in round 0 start after them.  Seeds after the first whose
+        // estimated cost leaves room before the plan's longest sector wait
+        // one sleep period before loading: the first sectors then load with
+        // less competition for bandwidth, and the wait cannot lengthen the
+        // launch by the cost model.
+        std::vector<double> item_cost_npdu;
+        plan.seeds.assign((size_t)G * waves, PoolSeed{-1, 0, 0, 0});
+        for (int g = 0; g < G; ++g) {
+            std::vector<int> distinct;
+            for (int i : members[g]) distinct.push_back(npdu[i].pages);
+            std::sort(distinct.begin(), distinct.end());
+            distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+            int step = 1;
+            auto rounded = [&](int p) { return std::min(plan.pool_pages, (p + step - 1) / step * step); };
+            for (;;) {
+                std::vector<int> r;
+                for (int p : distinct) r.push_back(rounded(p));
+                r.erase(std::unique(r.begin(), r.end()), r.end());
+                if ((int)r.size() <= kMaxLocalQueues) break;
+                ++step;
+            }
+            std::vector<std::pair<int, std::vector<int>>> lq;   // (pages, members in descending cost)
+            for (int i : members[g]) {
+                const int p = rounded(npdu[i].pages);
+                auto it = std::find_if(lq.begin(), lq.end(), [p](const auto& e) { return e.first == p; });
+                if (it == lq.end()) {
+                    lq.push_back({p, {}});
+                    it = lq.end() - 1;
+                }
+                it->second.push_back(i);
+            }
+            // members are in descending cost, so each queue's first item is its
+            // longest and the queues come out ordered by it
+            PoolGroup grp{(int)plan.queues.size(), (int)lq.size()};
+            plan.groups.push_back(grp);
+            std::vector<int> qfirst;
+            for (const auto& e : lq) {
+                qfirst.push_back((int)plan.items.size());
+                for (int i : e.second) {
+                    plan.items.push_back(npdu[i].item);
+                    item_cost_npdu.push_back(npdu[i].cost);
+                }
+                plan.queues.push_back(PoolQueue{qfirst.back(), (int)e.second.size(), e.first, 0});
+            }
+            int used = 0;
+            for (int w = 0; w < waves; ++w)
+                for (size_t q = 0; q < lq.size(); ++q) {
+                    PoolQueue& Q = plan.queues[grp.queue_first + q];
+                    if (Q.seeded < Q.count && used + Q.pages <= plan.pool_pages) {
+                        const int item = Q.first + Q.seeded;
                         const bool slack = env.pool.seed_sleep && w > 0 &&
-                                           item_cost[item] + kSeedSleepCycles <= bk.longest;
-                        plan.seeds[(size_t)g * waves + w] = PoolSeed{item, (int16_t)used[g], (int16_t)(slack ? 1 : 0)};
-                        used[g] += Q.pages;
-                        ++taken[q];
+                                           item_cost_npdu[item] + kSeedSleepCycles <= bk.longest;
+                        plan.seeds[(size_t)g * waves + w] =
+                            PoolSeed{item, (int16_t)used, (uint8_t)Q.pages, (uint8_t)(slack ? 1 : 0)};
+                        used += Q.pages;
+                        ++Q.seeded;
                         break;
                     }
                 }
-        for (size_t q = 0; q < plan.queues.size(); ++q) plan.queues[q].seeded = taken[q];
+        }
+        for (double c : item_cost_npdu) item_cost.push_back(c);
         plan.buckets.push_back(bk);
     }
     for (size_t i = 0; i < full.size();) {

@@ -28,12 +28,16 @@ struct FullVariantInfo {
 };
 
 // Where an NPDU sector's coordinates live, for sectors of at most n_max
-// points and windows k <= k_max: LDS records (xyz_in_lds = 1) or L2 (0).
-// The first entry (ascending n_max, then k_max) that covers a sector decides;
-// sectors no entry covers keep their coordinates in LDS up to 8192 points.
+// points and windows k <= k_max: LDS records (xyz_in_lds = 1) or outside LDS
+// (0: registers, or L2 where registers cannot serve).  The first entry
+// (ascending n_max, then k_max) that covers a sector decides; sectors no entry
+// covers hold their coordinates in registers up to kRegsDefaultMaxPoints
+// points with k <= 64 (in pooled shapes of at most 8 waves), else in LDS up
+// to 8192 points.
 struct NpduPlacement {
     int n_max, k_max, xyz_in_lds;
 };
+constexpr int kRegsDefaultMaxPoints = 4096;
 
 // Tunable policy of the pooled NPDU launch.
 struct PoolPolicy {
@@ -69,7 +73,8 @@ struct PlannedBucket {
 struct PlanTables {
     std::vector<WorkItem> items;
     std::vector<PlannedBucket> buckets;   // largest estimated cost first
-    std::vector<PoolQueue> queues;        // pooled sectors, highest priority first
+    std::vector<PoolGroup> groups;        // each pooled workgroup's queues
+    std::vector<PoolQueue> queues;        // every workgroup's queues, highest priority first
     std::vector<PoolSeed> seeds;          // first sector of each pooled wave, workgroup-major
     std::vector<CheckSeg> clouds;         // each descriptor's points
     int pool_pages = 0;                   // LDS pages of one pooled workgroup

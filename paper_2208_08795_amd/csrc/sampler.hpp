@@ -336,6 +336,15 @@ __device__ __forceinline__ void sample_sector(const float* __restrict__ xyz, int
 // A sector of the NPDU samplers belongs to one wave: its LDS stores need only
 // have completed before its own later loads, with no workgroup barrier (other
 // waves of the workgroup may be sampling other sectors).
+// The lane's index, opaque to the optimiser: what a sampler derives from it
+// is computed inside the sampler instead of being hoisted out of a caller's
+// work loop into registers held across every sampler inlined there.
+__device__ __forceinline__ int sampler_lane() {
+    int l = (int)(threadIdx.x & 63);
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 __device__ __forceinline__ void sector_lds_ready() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 }
@@ -361,7 +370,7 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
                                                           int k, int cur, int base,
                                                           int32_t* __restrict__ out, uint32_t* lds,
                                                           bool first_full, uint64_t* t_loaded) {
-    const int lane = threadIdx.x & 63;
+    const int lane = sampler_lane();
     const int nb = (n + 63) >> 6;
     const int np = npdu_padded_points(n);
     uint32_t* rec = static_cast<uint32_t*>(__builtin_assume_aligned(lds, 16));
@@ -512,6 +521,179 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     }
 }
 
+// NPDU on one sector for narrow windows with the sector's coordinates held in
+// vector registers instead of LDS:
+//   n <= 4096 (at most 64 blocks of 64 points), k <= 64.
+// Block b's coordinates sit in lane l (point 64 b + l) of element b >> 1 of
+// the even (b even) or the odd (b odd) register set: three vectors of 32
+// registers each, 192 VGPRs in all.  A wave-uniform element index reaches a
+// vector by relative register addressing (one index per set), and the two
+// adjacent blocks holding a window are always one even and one odd block.
+// LDS holds only D (npdu_lds_words(n, false) words), so a CU holds as many
+// of these sectors as it has waves, where 16-byte records in LDS would fit two
+// of 4096 points into its 160 KB.  The iteration is that of
+// sample_sector_npdu_narrow; the sample's coordinates come from the window
+// block holding it by a lane read.  Needs about 220 VGPRs: at most two waves
+// per SIMD.
+typedef float f32x32 __attribute__((ext_vector_type(32)));
+
+template <bool SHIFT>
+__device__ __forceinline__ void sample_sector_npdu_regs(const float* __restrict__ xyz, int n, int c, int k,
+                                                        int cur, int base, int32_t* __restrict__ out,
+                                                        uint32_t* lds, bool first_full, uint64_t* t_loaded) {
+    const int lane = sampler_lane();
+    const int nb = (n + 63) >> 6;
+    uint32_t* const rec = static_cast<uint32_t*>(__builtin_assume_aligned(lds, 16));
+    // Loads through a buffer resource bounded to the sector's 12 n bytes:
+    // points past the sector read as zeros.
+    const __amdgpu_buffer_rsrc_t xyz_rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xyz), (short)0, 12 * n, kBufferWord3);
+    const int lane12 = 12 * lane;
+    const uint32_t init = __float_as_uint(kInitialDistance);
+    float fx = 0.f, fy = 0.f, fz = 0.f;   // start point, for the full first update
+    if (first_full) {
+        fx = xyz[3 * cur];
+        fy = xyz[3 * cur + 1];
+        fz = xyz[3 * cur + 2];
+    }
+
+    // Load eight blocks per test of the block count, every load of the
+    // sector in flight at once.  Groups up to the one holding block nb (the
+    // padding block, read as zeros) are loaded, so every element a window
+    // can reach is defined.
+    f32x32 xe, ye, ze, xo, yo, zo;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        if (8 * g <= nb) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = 8 * g + u;
+                const v3u32 v = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, 768 * b + lane12, 0, 0);
+                if (b & 1) {
+                    xo[b >> 1] = __uint_as_float(v.x);
+                    yo[b >> 1] = __uint_as_float(v.y);
+                    zo[b >> 1] = __uint_as_float(v.z);
+                } else {
+                    xe[b >> 1] = __uint_as_float(v.x);
+                    ye[b >> 1] = __uint_as_float(v.y);
+                    ze[b >> 1] = __uint_as_float(v.z);
+                }
+            }
+        }
+    }
+    // D of every point (the start point's distance for the full first
+    // update, else 1e10) and of the padding block (0, never in a window).
+    for (int b = 0; b <= nb; b = __builtin_amdgcn_readfirstlane(b + 1)) {
+        const int j = 64 * b + lane;
+        uint32_t d = j < n ? init : 0u;
+        if (first_full && j < n) {
+            const int i = b >> 1;   // b < nb <= 64 here
+            const bool odd = (b & 1) != 0;
+            d = min(init, sq_dist_bits(odd ? xo[i] : xe[i], odd ? yo[i] : ye[i], odd ? zo[i] : ze[i], fx, fy, fz));
+        }
+        rec[j] = d;
+    }
+    sector_lds_ready();
+    if (t_loaded) *t_loaded = __builtin_amdgcn_s_memtime();
+
+    uint32_t bm = lane < nb ? init : 0u;   // block maxima (0 past the last block)
+    uint32_t bi = 0u;                      // position of each block's lowest-index maximum
+    const int below = k >> 1, above = k - (k >> 1);
+    uint32_t* const rec_lane = rec + lane;
+    uint32_t picks = (uint32_t)cur;
+    int s_first = 1;
+    if (first_full) {
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t d = rec_lane[64 * b];
+            const uint32_t g = wave_max(d);
+            bm = writelane(bm, g, b);
+            bi = writelane(bi, (uint32_t)__builtin_ctzll(ballot(d == g)), b);
+        }
+        if (c > 1) {
+            const uint32_t g = wave_max(bm);
+            const int wl = (int)__builtin_ctzll(ballot(bm == g));
+            cur = 64 * wl + (int)readlane(bi, wl);
+            picks = writelane(picks, (uint32_t)cur, 1);
+            s_first = 2;
+        }
+    }
+
+    auto step = [&](int s) {
+        int lo, hi;
+        if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
+            lo = cur - below;
+            hi = cur + above;
+            if (lo < 0) {
+                hi -= lo;
+                lo = 0;
+            }
+            if (hi > n - 1) {
+                lo = max(0, lo - (hi - (n - 1)));
+                hi = n - 1;
+            }
+        } else {
+            lo = max(0, cur - below);
+            hi = min(n - 1, cur + above);
+        }
+        // The window lies in blocks blo and blo + 1: the odd one is 2h + 1,
+        // the even one 2e.  For blo = 63 the second would be the padding block
+        // 64, which holds no registers; block 62 (outside the window, so
+        // re-reduced unchanged) takes its place.
+        const int blo = lo >> 6;
+        const int h = blo >> 1;
+        const int e = min(h + (blo & 1), 31);
+        const float ox = xo[h], oy = yo[h], oz = zo[h];
+        const float ex = xe[e], ey = ye[e], ez = ze[e];
+        const int lb = min(blo, 62);                 // the lower of the two blocks held
+        uint32_t* const wb = rec_lane + 64 * lb;
+        const uint32_t dl = wb[0], dh = wb[64];
+        const bool lodd = (lb & 1) != 0;             // the lower block is the odd one
+        const uint32_t de = lodd ? dh : dl, dod = lodd ? dl : dh;
+
+        const uint32_t g_out = wave_max((uint32_t)(lane - lb) > 1u ? bm : 0u);
+
+        // the sample: lane cur & 63 of whichever window block holds it
+        const bool codd = ((cur >> 6) & 1) != 0;
+        const int cl = cur & 63;
+        const float px = readlane(codd ? ox : ex, cl);
+        const float py = readlane(codd ? oy : ey, cl);
+        const float pz = readlane(codd ? oz : ez, cl);
+
+        const int span = hi - lo;
+        const uint32_t fe = min(de, sq_dist_bits(ex, ey, ez, px, py, pz));
+        const uint32_t fo = min(dod, sq_dist_bits(ox, oy, oz, px, py, pz));
+        const uint32_t ne = (uint32_t)(128 * e + lane - lo) <= (uint32_t)span ? fe : de;
+        const uint32_t no = (uint32_t)(128 * h + 64 + lane - lo) <= (uint32_t)span ? fo : dod;
+        wb[0] = lodd ? no : ne;
+        wb[64] = lodd ? ne : no;
+
+        uint32_t ge, go;
+        wave_max2(ne, no, ge, go);
+        const uint32_t ie = (uint32_t)__builtin_ctzll(ballot(ne == ge));
+        const uint32_t io = (uint32_t)__builtin_ctzll(ballot(no == go));
+        bm = writelane(bm, ge, 2 * e);
+        bi = writelane(bi, ie, 2 * e);
+        bm = writelane(bm, go, 2 * h + 1);
+        bi = writelane(bi, io, 2 * h + 1);
+
+        const uint32_t g = max(g_out, max(ge, go));
+        const int wl = (int)__builtin_ctzll(ballot(bm == g));
+        cur = 64 * wl + (int)readlane(bi, wl);
+        picks = writelane(picks, (uint32_t)cur, s);
+    };
+
+    for (int i0 = 0; i0 < c; i0 += 64) {
+        const int s_end = min(64, c - i0);
+        int s = i0 == 0 ? s_first : 0;
+        for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
+            step(s);
+            step(s + 1);
+        }
+        if (s < s_end) step(s);
+        if (lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
+    }
+}
+
 // NPDU on sectors of up to 4096 R points, any window: the loop of
 // sample_sector_npdu_narrow with R registers of block maxima (block 64 r + l
 // in lane l of register r; a window block's maximum goes in by a lane select
@@ -534,9 +716,9 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
     // by the range check; a 12-byte record is either wholly inside or outside.
     const __amdgpu_buffer_rsrc_t xyz_rsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xyz), (short)0, 12 * n, kBufferWord3);
-    const int lane12 = 12 * (int)(threadIdx.x & 63);
+    const int lane = sampler_lane();
+    const int lane12 = 12 * lane;
     constexpr int kWords = XYZ_IN_LDS ? 4 : 1;   // LDS words per point: {D, x, y, z} or D
-    const int lane = threadIdx.x & 63;
     const int nb = (n + 63) >> 6;
     const int np = npdu_padded_points(n);
     uint32_t* rec = static_cast<uint32_t*>(__builtin_assume_aligned(lds, 16));

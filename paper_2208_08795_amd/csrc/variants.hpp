@@ -61,13 +61,13 @@ struct PoolArgs {
     int32_t* out_all;
     const PoolRound* rounds;   // several rounds: per-round points and outputs, or nullptr
     const WorkItem* items;
+    const PoolGroup* groups;   // one per workgroup
     const PoolQueue* queues;
-    unsigned* qtaken;          // queue counters, kRoundCounters per round
-    const PoolSeed* seeds;
+    const PoolSeed* seeds;     // W per workgroup, workgroup-major
     unsigned* status;          // the plan's status word (workspace), set when a wave gives up
     unsigned* dev_status;      // the device's failure word, set alike
     SectorStamp* stamps;       // per plan item (single round only), or nullptr
-    int nrounds, nq, seed_groups, pool_pages;
+    int nrounds, pool_pages;
     unsigned spin_limit;
     int seed_priority;         // issue priority (0..3) of the wave running its workgroup's first seed
 };

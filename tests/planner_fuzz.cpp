@@ -3,7 +3,8 @@
 // tests/test_planner_host.py.  For random batches (clouds of 1..32768 points,
 // mixed plain FPS / AFPS / NPDU with every reading flag, random starts), every
 // occupancy budget and pool policy, it asserts that the plan covers every
-// sector exactly once with the Sec. III-B split, that every work item, queue,
+// sector exactly once with the Sec. III-B split, that every pooled sector
+// belongs to exactly one workgroup's queues, that every work item, queue,
 // seed and page range stays inside the workspace and the LDS pool, and that
 // corrupted descriptors are rejected.  Exit status 0 = every check held.
 #include <algorithm>
@@ -137,11 +138,11 @@ void check_plan(const std::vector<afps_cloud_desc>& d, const PlannerEnv& env, co
             CHECK(it.c >= 1 && it.c <= it.n, "cloud %zu sector %d samples %d of %d", b, s, it.c, it.n);
             CHECK(it.start == c.start % ns, "cloud %zu sector %d start", b, s);
             CHECK(it.k == (k < 0 ? -1 : std::min(k, 2 * ns)), "cloud %zu sector %d k", b, s);
-            CHECK((it.flags & ~kItemXyzInL2) == (k < 0 ? 0 : flags), "cloud %zu sector %d flags", b, s);
-            const bool l2 = (it.flags & kItemXyzInL2) != 0;
-            CHECK(!l2 || (k >= 0 && npdu_r_for(ns) <= 2), "L2 flag on a sector that cannot hold it");
+            CHECK((it.flags & ~kItemXyzNotInLds) == (k < 0 ? 0 : flags), "cloud %zu sector %d flags", b, s);
+            const bool out = (it.flags & kItemXyzNotInLds) != 0;
+            CHECK(!out || (k >= 0 && npdu_r_for(ns) <= 2), "placement flag on a sector that cannot hold it");
             if (k >= 0 && npdu_r_for(ns) <= 2)
-                CHECK(l2 == !npdu_xyz_in_lds(env.pool, ns, it.k), "placement of cloud %zu sector %d", b, s);
+                CHECK(out == !npdu_xyz_in_lds(env.pool, ns, it.k), "placement of cloud %zu sector %d", b, s);
             CHECK(it.out_offset + it.c <= c.out_offset + c.c && it.xyz_offset + it.n <= c.xyz_offset + c.n,
                   "sector outside its cloud");
             ++sectors;
@@ -179,50 +180,67 @@ void check_plan(const std::vector<afps_cloud_desc>& d, const PlannerEnv& env, co
     for (size_t i = 0; i < owner.size(); ++i) CHECK(owner[i] >= 0, "item %zu in no bucket", i);
     CHECK(pool_buckets <= 1, "pool buckets");
 
-    // queues and seeds: together exactly the NPDU items, pages in the pool
+    // workgroups, queues and seeds: together exactly the NPDU items, pages in the pool
     int npdu_items = 0;
     for (const auto& it : t.items) npdu_items += it.k >= 0;
-    CHECK((int)t.queues.size() <= kMaxPoolQueues, "queues");
+    int pool_grid = 0;
+    for (const auto& bk : t.buckets)
+        if (bk.pool()) pool_grid = bk.grid;
+    CHECK((int)t.groups.size() == pool_grid && pool_grid <= kMaxPoolGroups, "%zu workgroups, grid %d",
+          t.groups.size(), pool_grid);
     std::vector<int> seen(t.items.size(), 0);
     std::vector<int> in_queue(t.items.size(), 0);
-    int next_first = 0;
-    for (const auto& q : t.queues) {
-        CHECK(q.first >= 0 && q.count >= 1 && q.first + q.count <= npdu_items, "queue range");
-        CHECK(q.seeded >= 0 && q.seeded <= q.count, "queue seeded %d of %d", q.seeded, q.count);
-        CHECK(q.pages >= 1 && q.pages <= t.pool_pages, "queue pages %d of %d", q.pages, t.pool_pages);
-        CHECK(q.first == next_first, "queues tile the NPDU items in order");
-        next_first = q.first + q.count;
-        for (int i = q.first; i < q.first + q.count && i < (int)t.items.size(); ++i) {
-            ++in_queue[i];
-            if (i >= q.first + q.seeded) ++seen[i];   // round 0 queues only the unseeded ones
-            const WorkItem& it = t.items[i];
-            CHECK(npdu_pool_pages(it.n, npdu_item_xyz_in_lds(it.n, it.flags)) == q.pages, "item pages");
+    std::vector<int> group_of(t.items.size(), -1);
+    int next_first = 0, next_queue = 0;
+    for (size_t g = 0; g < t.groups.size(); ++g) {
+        const PoolGroup& grp = t.groups[g];
+        CHECK(grp.queue_first == next_queue && grp.queues >= 1 && grp.queues <= kMaxLocalQueues,
+              "workgroup %zu queues [%d, +%d)", g, grp.queue_first, grp.queues);
+        next_queue = grp.queue_first + grp.queues;
+        std::set<int> pages_seen;
+        for (int qi = grp.queue_first; qi < grp.queue_first + grp.queues && qi < (int)t.queues.size(); ++qi) {
+            const PoolQueue& q = t.queues[qi];
+            CHECK(q.first >= 0 && q.count >= 1 && q.first + q.count <= npdu_items, "queue range");
+            CHECK(q.seeded >= 0 && q.seeded <= q.count, "queue seeded %d of %d", q.seeded, q.count);
+            CHECK(q.pages >= 1 && q.pages <= t.pool_pages, "queue pages %d of %d", q.pages, t.pool_pages);
+            CHECK(q.first == next_first, "queues tile the NPDU items in order");
+            CHECK(pages_seen.insert(q.pages).second, "two queues of %d pages in workgroup %zu", q.pages, g);
+            next_first = q.first + q.count;
+            for (int i = q.first; i < q.first + q.count && i < (int)t.items.size(); ++i) {
+                ++in_queue[i];
+                group_of[i] = (int)g;
+                if (i >= q.first + q.seeded) ++seen[i];   // round 0 queues only the unseeded ones
+                const WorkItem& it = t.items[i];
+                CHECK(npdu_pool_pages(it.n, npdu_item_xyz_in_lds(it.n, it.flags)) <= q.pages, "item pages");
+            }
         }
     }
+    CHECK(next_queue == (int)t.queues.size(), "workgroups cover the queues");
     CHECK(next_first == npdu_items, "queues cover the NPDU items");
     for (int i = 0; i < npdu_items; ++i) CHECK(in_queue[i] == 1, "NPDU item %d in %d queues (later rounds)", i, in_queue[i]);
     if (npdu_items) {
         const int waves = t.pool_waves;
-        CHECK((int)t.seeds.size() % waves == 0, "seed table shape");
-        CHECK((int)t.seeds.size() <= kMaxPoolSeedGroups * kMaxPoolWaves, "seed table size");
-        const int groups = (int)t.seeds.size() / waves;
-        for (int g = 0; g < groups; ++g) {
+        CHECK((int)t.seeds.size() == pool_grid * waves, "seed table shape");
+        for (int g = 0; g < pool_grid; ++g) {
             std::vector<std::pair<int, int>> ranges;
             for (int w = 0; w < waves; ++w) {
                 const PoolSeed& sd = t.seeds[(size_t)g * waves + w];
                 if (sd.item < 0) continue;
                 CHECK(sd.item < npdu_items, "seed item");
-                bool front = false;   // a seed is among the first `seeded` items of its queue
-                for (const auto& q : t.queues) front |= sd.item >= q.first && sd.item < q.first + q.seeded;
-                CHECK(front, "seed %d is not at the front of its queue", sd.item);
                 if (sd.item >= npdu_items) continue;
+                CHECK(group_of[sd.item] == g, "seed %d of workgroup %d is another workgroup's", sd.item, g);
+                bool front = false;   // a seed is among the first `seeded` items of its queue, and takes its pages
+                const PoolGroup& grp = t.groups[g];
+                for (int qi = grp.queue_first; qi < grp.queue_first + grp.queues; ++qi) {
+                    const PoolQueue& q = t.queues[qi];
+                    if (sd.item >= q.first && sd.item < q.first + q.seeded) front = sd.pages == q.pages;
+                }
+                CHECK(front, "seed %d is not at the front of its queue with its pages", sd.item);
                 ++seen[sd.item];
-                const WorkItem& it = t.items[sd.item];
-                const int p = npdu_pool_pages(it.n, npdu_item_xyz_in_lds(it.n, it.flags));
-                CHECK(sd.page >= 0 && sd.page + p <= t.pool_pages, "seed pages [%d, %d) of %d", sd.page, sd.page + p,
-                      t.pool_pages);
+                CHECK(sd.page >= 0 && sd.page + sd.pages <= t.pool_pages, "seed pages [%d, %d) of %d", sd.page,
+                      sd.page + sd.pages, t.pool_pages);
                 CHECK(sd.sleeps == 0 || (sd.sleeps == 1 && env.pool.seed_sleep && w > 0), "seed sleeps");
-                ranges.push_back({sd.page, sd.page + p});
+                ranges.push_back({sd.page, sd.page + sd.pages});
             }
             std::sort(ranges.begin(), ranges.end());
             for (size_t r = 1; r < ranges.size(); ++r) CHECK(ranges[r - 1].second <= ranges[r].first, "seed pages overlap");
@@ -246,7 +264,7 @@ int main(int argc, char** argv) {
         std::string err;
         const int rc = build_plan(d.data(), (int32_t)d.size(), env, &t, &err);
         // valid descriptors fail only where a sector exceeds the LDS pool of a
-        // (small, random) device, or there are too many NPDU sector sizes
+        // (small, random) device
         if (rc != AFPS_OK) {
             CHECK(rc == AFPS_ERR_UNSUPPORTED, "iteration %d: status %d (%s)", it, rc, err.c_str());
             ++rejected;

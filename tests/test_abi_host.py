@@ -87,8 +87,16 @@ def test_host_validation_without_gpu(L):
     assert L.afps_plan_launch_noalloc(None, dummy, dummy, None) == -1
     assert L.afps_plan_status(None, dummy, None) == -1
     assert L.afps_plan_launch_stamped(None, dummy, dummy, dummy, dummy, 64, None) == -1
-    header = 256 + 128 * 4 + 128 * 16 + 512 * 16 * 8   # counters, queue table, seeds (512 groups x 16 waves)
-    assert L.afps_noalloc_max_items() == ((1 << 20) - header) // 40
+    # the no-alloc entry point takes plans whose workspace fits its 1 MiB scratch:
+    # 256 B of counters, 512 pooled workgroups (8 B each) and their seeds (16
+    # waves of 8 B), then 40 B per work item and at most one 16 B queue per item
+    header = 256 + 512 * 8 + 512 * 16 * 8
+    L.afps_workspace_bytes_for_items.restype = ctypes.c_size_t
+    L.afps_workspace_bytes_for_items.argtypes = [ctypes.c_int32]
+    assert L.afps_workspace_bytes_for_items(1) == (header + 40 + 8 + 16 + 255) // 256 * 256
+    cap = L.afps_noalloc_max_items()
+    assert L.afps_workspace_bytes_for_items(cap) <= 1 << 20 < L.afps_workspace_bytes_for_items(cap + 1)
+    assert cap == ((1 << 20) - header) // 56
     # grouping: arguments checked on the host; no centres launches nothing
     assert L.afps_ball_query(None, 10, dummy, 4, 1.0, 8, -1, dummy, None, None) == -1
     assert L.afps_ball_query(dummy, 10, None, 4, 1.0, 8, -1, dummy, None, None) == -1

@@ -558,24 +558,32 @@ def test_autotuner_choices_stay_exact(B, torch_dev):
         B.tune_reset()
 
 
-@pytest.mark.parametrize("placement", ["all_l2", "l2_up_to_2048", "l2_above_2048"])
-def test_pooled_sectors_with_tuned_coordinate_placement(B, torch_dev, placement):
-    """NPDU sectors whose coordinates the tuning table sends to L2 (only the
-    distances in LDS) in one pooled launch with sectors that keep them in
-    LDS: sizes on both sides of every threshold, every reading, windows inside
-    two blocks and wider; every index against the oracle, graph replays."""
+@pytest.mark.parametrize("shape", [(8, 1), (16, 1)])
+@pytest.mark.parametrize("placement", ["all_out", "out_up_to_2048", "out_above_2048", "all_lds"])
+def test_pooled_sectors_with_tuned_coordinate_placement(B, torch_dev, placement, shape):
+    """NPDU sectors whose coordinates the tuning table keeps out of LDS (only
+    the distances in LDS; the coordinates in registers up to 4096 points with
+    k <= 64 in launches of at most 8 waves per workgroup, else read from L2)
+    in one pooled launch with sectors that keep them in LDS: sizes on both
+    sides of every threshold, every reading, windows inside two blocks and
+    wider, a 16-wave shape (no register sets: L2 instead); every index
+    against the oracle, graph replays."""
     torch, dev = torch_dev
     B.tune_reset()
     try:
-        if placement == "all_l2":
+        B.set_pool_policy(shape[0], shape[1], True, 3)
+        if placement == "all_out":
             B.tune_npdu(8192, 1 << 30, False)
-        elif placement == "l2_up_to_2048":
+        elif placement == "out_up_to_2048":
             B.tune_npdu(2048, 1 << 30, False)
-        else:
+            B.tune_npdu(8192, 1 << 30, True)
+        elif placement == "out_above_2048":
             B.tune_npdu(2048, 1 << 30, True)
             B.tune_npdu(8192, 1 << 30, False)
-        assert B.npdu_xyz_in_lds(1000, 32) == (placement == "l2_above_2048")
-        assert B.npdu_xyz_in_lds(5000, 32) == (placement == "l2_up_to_2048")
+        else:
+            B.tune_npdu(8192, 1 << 30, True)
+        assert B.npdu_xyz_in_lds(1000, 32) == (placement in ("out_above_2048", "all_lds"))
+        assert B.npdu_xyz_in_lds(5000, 32) == (placement in ("out_up_to_2048", "all_lds"))
         sizes = [4096, 4097, 2048, 2049, 8192, 777, 65, 1, 3000, 6000, 12000, 1500]
         ms = [1, 1, 1, 1, 1, 1, 1, 1, 2, 3, 2, 1]
         ks = [32, 64, 8, 100, 32, 0, 65, 0, 200, 17, 33, 64]
