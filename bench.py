@@ -51,10 +51,13 @@ LDS_BYTES_PER_CLK_PER_CU = 128.0
 # A wave64 VALU instruction occupies its SIMD's vector ALU for 4 cycles.
 VALU_CYCLES_PER_INST = 4
 # Bytes one LDS instruction of the NPDU loop moves, on average over its mix per
-# iteration (one broadcast 16-byte read of the sample, two 16-byte reads of a
-# window block each, one paired 4-byte write of the window's distances:
-# 1024 + 2 x 1024 + 512 bytes of lanes in 4 instructions).
-LDS_BYTES_PER_INST = (1024 + 2 * 1024 + 512) / 4
+# iteration.  Coordinates in LDS records: one broadcast 16-byte read of the
+# sample, two 16-byte reads of a window block each, one paired 4-byte write
+# of the window's distances (1024 + 2 x 1024 + 512 bytes of lanes in 4
+# instructions).  Coordinates in registers: one paired 4-byte read and one
+# paired 4-byte write of the window's distances (512 + 512 in 2).
+LDS_BYTES_PER_INST_RECORDS = (1024 + 2 * 1024 + 512) / 4
+LDS_BYTES_PER_INST_REGS = (512 + 512) / 2
 
 
 def log(msg):
@@ -78,12 +81,14 @@ def _event_ms(torch, run, stream, reps):
     return ms
 
 
-def npdu_counts(sizes, cs, out_np, offsets, m, k):
+def npdu_counts(sizes, cs, out_np, offsets, m, k, records_above=None):
     """Work of one pass of AFPS-NPDU over the batch, counted from its picks:
     distance updates (the exact window sizes), iterations, the window and
     block-maximum compares of the argmax (k + 1 + ceil(n_s / 64) per
-    iteration) and the compares of an Algorithm-1 scan ((c_s - 1) n_s)."""
-    upd = iters = win_cmp = blk_cmp = scan_cmp = 0
+    iteration) and the compares of an Algorithm-1 scan ((c_s - 1) n_s).
+    With records_above, `updates_records` counts the updates of sectors of
+    more points, whose coordinates sit in LDS records (the others' only D)."""
+    upd = iters = win_cmp = blk_cmp = scan_cmp = upd_rec = 0
     for n, c, o in zip(sizes, cs, offsets):
         qn, rn, qc, rc = n // m, n % m, c // m, c % m
         for s in range(m):
@@ -92,13 +97,16 @@ def npdu_counts(sizes, cs, out_np, offsets, m, k):
             cur = out_np[o + oo:o + oo + cc - 1].astype(np.int64) - b
             lo = np.maximum(0, cur - k // 2)
             hi = np.minimum(ns - 1, cur + (k - k // 2))
-            upd += int((hi - lo + 1).sum())
+            u = int((hi - lo + 1).sum())
+            upd += u
+            if records_above is not None and ns > records_above:
+                upd_rec += u
             iters += cc - 1
             win_cmp += (cc - 1) * (k + 1)
             blk_cmp += (cc - 1) * (-(-ns // 64))
             scan_cmp += (cc - 1) * ns
     return {"updates": upd, "iterations": iters, "ops": 9 * upd + win_cmp + blk_cmp,
-            "alg1_scan_ops": 9 * upd + scan_cmp}
+            "alg1_scan_ops": 9 * upd + scan_cmp, "updates_records": upd_rec}
 
 
 def fps_ops(sizes, cs):
@@ -643,7 +651,7 @@ def main():
     res["sclk_mhz_after_timed_steps"] = sclk
 
     # ---- roofline of the dominant kernel, on the timed launch's own time
-    cnt = npdu_counts(sizes, cs, out_np, plan.offsets, M, K)
+    cnt = npdu_counts(sizes, cs, out_np, plan.offsets, M, K, records_above=regs_up_to)
     stamps = None
     wall_khz = int(L.afps_wall_clock_khz())
     if not args.only_timed:
@@ -655,7 +663,9 @@ def main():
     round_s = launch_s / steps
     ops_launch = cnt["ops"] * steps
     hbm_round = 12 * sum(sizes) + 4 * total_samples + 40 * plan.items
-    lds_round = 20 * cnt["updates"]              # 16 B read (x, y, z, D) + 4 B written per update
+    # per update: 16 B read (x, y, z, D) + 4 B written with LDS records, 4 + 4 B
+    # (D only) with the coordinates in registers
+    lds_round = 20 * cnt["updates_records"] + 8 * (cnt["updates"] - cnt["updates_records"])
     lds_peak_tbs = CUS * LDS_BYTES_PER_CLK_PER_CU * clock_ghz * 1e9 / 1e12
     rec = counter_record("%s, registers up to %d" % (label, regs_up_to))
     roof = {"bound": "alu", "kernel": label, "achieved": ops_launch / launch_s / 1e12, "peak": VALU_PEAK_TOPS,
@@ -681,7 +691,8 @@ def main():
     if rec:
         valu = rec["SQ_INSTS_VALU_per_round"]
         roof["valu_issue_frac"] = valu * VALU_CYCLES_PER_INST / (CUS * SIMDS_PER_CU * round_s * clock_ghz * 1e9)
-        kb = rec["SQ_INSTS_LDS_per_round"] * LDS_BYTES_PER_INST
+        per_inst = LDS_BYTES_PER_INST_REGS if cnt["updates_records"] == 0 else LDS_BYTES_PER_INST_RECORDS
+        kb = rec["SQ_INSTS_LDS_per_round"] * per_inst
         roof["lds"].update({"kernel_bytes_per_launch": kb * steps, "kernel_frac": kb / round_s / 1e12 / lds_peak_tbs})
         roof["counters_per_round"] = {k: v for k, v in rec.items() if k.endswith("_per_round")}
         roof["counters_note"] = ("SQ and traffic counters per round from the committed rocprofv3 record of this "

@@ -23,6 +23,10 @@ def test_npdu_counts_by_hand():
     assert c["updates"] == 8 and c["iterations"] == 3
     assert c["ops"] == 9 * 8 + 3 * (2 + 1) + 3 * 1           # window + one 64-point block per iteration
     assert c["alg1_scan_ops"] == 9 * 8 + 3 * 10
+    # LDS-record updates: sectors of more points than the register bound
+    assert bench.npdu_counts([10], [4], out, [0], 1, 2, records_above=9)["updates_records"] == 8
+    assert bench.npdu_counts([10], [4], out, [0], 1, 2, records_above=10)["updates_records"] == 0
+    assert c["updates_records"] == 0
     # two sectors of 70 and 69 points (M = 2, N = 139), two samples each: one
     # iteration per sector, two blocks in the first, two in the second
     out = np.array([0, 35, 70, 100], dtype=np.int32)

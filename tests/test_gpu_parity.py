@@ -626,7 +626,7 @@ def test_npdu_tuner_choices_stay_exact(B, torch_dev):
     try:
         res = autotune.tune_npdu(xyz, sizes, cs, [8] * 32, [32] * 32, [0] * 32, rounds=3, reps=1)
         print("npdu tuner best", res["best"], "of", len(res["rows"]), flush=True)
-        assert len(res["rows"]) >= 3 * len(autotune.L2_UP_TO)
+        assert len(res["rows"]) >= 3 * len(autotune.REGS_UP_TO)
         plan = _batch_case(B, torch, dev, clouds, cs, [8] * 32, [32] * 32, [0] * 32, graph_replays=1)
         assert (plan.pool_waves, plan.pool_groups) == res["best"][0]
     finally:
