@@ -100,7 +100,8 @@ __device__ __forceinline__ T* global_ptr(int64_t bits) {
 // call for; `lds` is the first of its pages; LR points per lane in flight
 // while the sector loads.  Coordinates kept out of LDS live in registers
 // (REGS: kernels of at most two waves per SIMD, sectors of at most 4096
-// points, k <= 64), else they are read from L2.
+// points, k <= 64), else they are read from L2 (by the narrow loop for such
+// sectors without REGS).
 template <int LR, bool REGS>
 __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int32_t* __restrict__ out_all,
                                          const WorkItem& wi, uint32_t* lds, uint64_t* t_loaded) {
@@ -119,6 +120,13 @@ __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int3
                 else
                     sample_sector_npdu_regs<false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
                                                    (f & kNpduFirstFull) != 0, t_loaded);
+            } else if (wi.k <= 64) {
+                if (f & kNpduShiftEdges)
+                    sample_sector_npdu_narrow_l2<true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
+                                                       (f & kNpduFirstFull) != 0, t_loaded);
+                else
+                    sample_sector_npdu_narrow_l2<false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
+                                                        (f & kNpduFirstFull) != 0, t_loaded);
             } else {
                 sample_sector_npdu<1, false, LR>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
             }

@@ -521,6 +521,136 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
     }
 }
 
+// NPDU on one sector for narrow windows with the coordinates read from
+// global memory (L2) and only D in LDS (npdu_lds_words(n, false) words):
+//   n <= 4096, k <= 64.
+// The loop of sample_sector_npdu_narrow with its three LDS record reads
+// replaced by loads: the sample's 12 bytes (one wave-uniform load) and the
+// two window blocks' (one 12-byte load per lane each, through a buffer
+// resource bounded to the sector, so the padding block reads zeros).  The
+// memory round trip is on every iteration's path, which many waves per SIMD
+// hide; the sector takes a quarter of the LDS of 16-byte records.
+template <bool SHIFT>
+__device__ __forceinline__ void sample_sector_npdu_narrow_l2(const float* __restrict__ xyz, int n, int c, int k,
+                                                             int cur, int base, int32_t* __restrict__ out,
+                                                             uint32_t* lds, bool first_full, uint64_t* t_loaded) {
+    const int lane = sampler_lane();
+    const int nb = (n + 63) >> 6;
+    const int np = npdu_padded_points(n);
+    uint32_t* const rec = static_cast<uint32_t*>(__builtin_assume_aligned(lds, 16));
+    const __amdgpu_buffer_rsrc_t xyz_rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(xyz), (short)0, 12 * n, kBufferWord3);
+    const int lane12 = 12 * lane;
+    const uint32_t init = __float_as_uint(kInitialDistance);
+    // D of every point: the start point's distance for the full first
+    // update (coordinates read once here), else 1e10; padding 0.
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    if (first_full) {
+        fx = xyz[3 * cur];
+        fy = xyz[3 * cur + 1];
+        fz = xyz[3 * cur + 2];
+    }
+    for (int j = lane; j < np; j += 64) {
+        uint32_t d = j < n ? init : 0u;
+        if (first_full && j < n) d = min(init, sq_dist_bits(xyz[3 * j], xyz[3 * j + 1], xyz[3 * j + 2], fx, fy, fz));
+        rec[j] = d;
+    }
+    sector_lds_ready();
+    if (t_loaded) *t_loaded = __builtin_amdgcn_s_memtime();
+
+    uint32_t bm = lane < nb ? init : 0u;
+    uint32_t bi = 0u;
+    const int below = k >> 1, above = k - (k >> 1);
+    uint32_t* const rec_lane = rec + lane;
+    uint32_t picks = (uint32_t)cur;
+    int s_first = 1;
+    if (first_full) {
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t d = rec_lane[64 * b];
+            const uint32_t g = wave_max(d);
+            bm = writelane(bm, g, b);
+            bi = writelane(bi, (uint32_t)__builtin_ctzll(ballot(d == g)), b);
+        }
+        if (c > 1) {
+            const uint32_t g = wave_max(bm);
+            const int wl = (int)__builtin_ctzll(ballot(bm == g));
+            cur = 64 * wl + (int)readlane(bi, wl);
+            picks = writelane(picks, (uint32_t)cur, 1);
+            s_first = 2;
+        }
+    }
+
+    auto step = [&](int s) {
+        // the sample's coordinates: one wave-uniform load at a 32-bit offset
+        const float* const p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(xyz) + (uint32_t)(12 * cur));
+        const float px = p[0], py = p[1], pz = p[2];
+        int lo, hi;
+        if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
+            lo = cur - below;
+            hi = cur + above;
+            if (lo < 0) {
+                hi -= lo;
+                lo = 0;
+            }
+            if (hi > n - 1) {
+                lo = max(0, lo - (hi - (n - 1)));
+                hi = n - 1;
+            }
+        } else {
+            lo = max(0, cur - below);
+            hi = min(n - 1, cur + above);
+        }
+        const int blo = lo >> 6;
+        const int off = 768 * blo + lane12;   // block blo + 1 at 768 bytes further
+        const v3u32 A = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off, 0, 0);
+        const v3u32 B = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off + 768, 0, 0);
+        uint32_t* const wb = rec_lane + 64 * blo;
+        const uint32_t da = wb[0], db = wb[64];
+
+        const uint32_t g_out = wave_max((uint32_t)(lane - blo) > 1u ? bm : 0u);
+
+        const int t = lane - (lo & 63);
+        const int span = hi - lo;
+        const uint32_t e0 = min(da, sq_dist_bits(__uint_as_float(A.x), __uint_as_float(A.y), __uint_as_float(A.z),
+                                                 px, py, pz));
+        const uint32_t e1 = min(db, sq_dist_bits(__uint_as_float(B.x), __uint_as_float(B.y), __uint_as_float(B.z),
+                                                 px, py, pz));
+        const uint32_t d0 = (uint32_t)t <= (uint32_t)span ? e0 : da;
+        const uint32_t d1 = t <= span - 64 ? e1 : db;
+        wb[0] = d0;
+        wb[64] = d1;
+
+        uint32_t g0, g1;
+        wave_max2(d0, d1, g0, g1);
+        const uint32_t i0 = (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+        const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+        // Block blo+1 may be the padding block (g1 = 0) or, for n = 4096,
+        // lane 64, which does not exist: then it goes to lane 63 first and
+        // block blo = 63 overwrites it.
+        const int l1 = min(blo + 1, 63);
+        bm = writelane(bm, g1, l1);
+        bi = writelane(bi, i1, l1);
+        bm = writelane(bm, g0, blo);
+        bi = writelane(bi, i0, blo);
+
+        const uint32_t g = max(g_out, max(g0, g1));
+        const int wl = (int)__builtin_ctzll(ballot(bm == g));
+        cur = 64 * wl + (int)readlane(bi, wl);
+        picks = writelane(picks, (uint32_t)cur, s);
+    };
+
+    for (int i0 = 0; i0 < c; i0 += 64) {
+        const int s_end = min(64, c - i0);
+        int s = i0 == 0 ? s_first : 0;
+        for (; s + 1 < s_end; s = __builtin_amdgcn_readfirstlane(s + 2)) {
+            step(s);
+            step(s + 1);
+        }
+        if (s < s_end) step(s);
+        if (lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
+    }
+}
+
 // NPDU on one sector for narrow windows with the sector's coordinates held in
 // vector registers instead of LDS:
 //   n <= 4096 (at most 64 blocks of 64 points), k <= 64.
