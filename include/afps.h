@@ -340,8 +340,8 @@ void afps_tune_reset(void);   /* forgets every tuned entry and the pool policy (
  * launches of at most 8 waves per workgroup, else they are read from L2).
  * The entry with the smallest n_s_max (then k_max) that covers a sector
  * decides; without one, sectors of at most 4096 points with k <= 64 hold
- * their coordinates in registers (LDS when the pool policy asks for 12 or 16
- * waves) and other sectors up to 8192 points in LDS.  Read from
+ * their coordinates out of LDS (registers in pooled launches of at most 8
+ * waves per workgroup, else L2) and other sectors up to 8192 points in LDS.  Read from
  * AFPS_TUNE_CACHE as lines "npdu n_s_max k_max xyz_in_lds".  AFPS_ERR_ARG
  * for bad values.  afps_npdu_xyz_in_lds reports the placement a sector would
  * get.
@@ -356,10 +356,14 @@ void afps_tune_npdu_clear(void);
  * Policy of the pooled NPDU launch of batch plans created afterwards:
  *   waves, groups_per_cu  the launch shape: one workgroup per CU of 4, 8, 12
  *                         or 16 waves (one to four per SIMD) owning all of
- *                         the CU's LDS pages, or two of 4 waves owning half
- *                         each (used when every sector fits half); 0, 0 =
- *                         chosen from the plan's occupancy budget and its
- *                         sectors (afps_set_plan_occupancy)
+ *                         the CU's LDS pages, or two of 4, 12 or 16 waves
+ *                         owning half each (used when every sector fits half;
+ *                         two of 12 or 16, six or eight waves per SIMD, only
+ *                         when every NPDU sector has at most 4096 points,
+ *                         k <= 64 and its coordinates out of LDS: a light
+ *                         kernel that holds only that loop); 0, 0 = chosen
+ *                         from the plan's occupancy budget and its sectors
+ *                         (afps_set_plan_occupancy)
  *   seed_sleep            1 = first sectors with slack before the plan's
  *                         longest one wait a sleep period before loading
  *   seed_priority         issue priority 0..3 of the wave running its

@@ -147,7 +147,7 @@ def tune_occupancy(xyz_all, sizes, cs, ms, ks, starts, factors=(0.0, 1.0, 2.0, 4
 # placements (sectors of at most n points hold their coordinates out of LDS:
 # in registers where the kernel can, else L2; larger ones in LDS records; 0 =
 # every sector in LDS) that tune_npdu tries.
-POOL_SHAPES = ((8, 1), (4, 1), (4, 2), (12, 1), (16, 1))
+POOL_SHAPES = ((8, 1), (4, 1), (4, 2), (12, 1), (16, 1), (12, 2), (16, 2))
 REGS_UP_TO = (4096, 2048, 1024, 0)
 SEEDING = ((True, 3), (False, 3), (True, 0), (False, 0))
 

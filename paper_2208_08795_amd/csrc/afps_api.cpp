@@ -619,7 +619,7 @@ int afps_tune_npdu(int32_t n_s_max, int32_t k_max, int32_t xyz_in_lds) {
 
 int afps_set_pool_policy(int32_t waves, int32_t groups_per_cu, int32_t seed_sleep, int32_t seed_priority) {
     if (!valid_pool_policy(waves, groups_per_cu, seed_sleep, seed_priority))
-        return fail(AFPS_ERR_ARG, "pool shape must be (0, 0), (4|8|12|16 waves, 1 group) or (4 waves, 2 groups); "
+        return fail(AFPS_ERR_ARG, "pool shape must be (0, 0), (4|8|12|16 waves, 1 group) or (4|12|16 waves, 2 groups); "
                                   "seed_sleep 0|1; seed_priority 0..3");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file_locked();
@@ -743,6 +743,7 @@ struct afps_plan {
     int pool_pages = 0;               // LDS pages of one pooled workgroup
     int pool_groups = 0;              // pooled workgroups per CU (1 or 2; 0 without NPDU sectors)
     int pool_waves = 0;
+    bool pool_lite = false;           // the light pooled kernel (every NPDU sector npdu_item_lite)
     int seed_priority = 0;
     size_t ws_bytes = 0;
     int device = 0;
@@ -809,13 +810,14 @@ int afps_plan_create(const afps_cloud_desc* descs, int32_t batch, afps_plan** pl
     plan->pool_pages = t.pool_pages;
     plan->pool_groups = t.pool_groups;
     plan->pool_waves = t.pool_waves;
+    plan->pool_lite = t.pool_lite;
     plan->seed_priority = t.seed_priority;
     plan->ws_bytes = t.ws_bytes;
     for (const auto& bk : plan->buckets) {
         const void* k = nullptr;
         if (bk.pool()) {
             for (const auto& v : registry().pool)
-                if (v.waves == plan->pool_waves) k = v.kernel;
+                if (v.waves == plan->pool_waves && v.lite == plan->pool_lite) k = v.kernel;
         } else {
             k = registry().full[bk.variant].persistent;
         }

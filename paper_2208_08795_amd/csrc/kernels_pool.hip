@@ -102,12 +102,21 @@ __device__ __forceinline__ T* global_ptr(int64_t bits) {
 // (REGS: kernels of at most two waves per SIMD, sectors of at most 4096
 // points, k <= 64), else they are read from L2 (by the narrow loop for such
 // sectors without REGS).
-template <int LR, bool REGS>
+template <int LR, bool REGS, bool LITE>
 __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int32_t* __restrict__ out_all,
                                          const WorkItem& wi, uint32_t* lds, uint64_t* t_loaded) {
     const float* xyz = xyz_all + 3 * wi.xyz_offset;
     int32_t* out = out_all + wi.out_offset;
     const int f = wi.flags & ~kItemXyzNotInLds;
+    if constexpr (LITE) {   // the plan holds npdu_item_lite sectors only
+        if (f & kNpduShiftEdges)
+            sample_sector_npdu_narrow_l2<true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
+                                               (f & kNpduFirstFull) != 0, t_loaded);
+        else
+            sample_sector_npdu_narrow_l2<false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
+                                                (f & kNpduFirstFull) != 0, t_loaded);
+        return;
+    }
     const bool in_lds = npdu_item_xyz_in_lds(wi.n, wi.flags);
     switch (npdu_r_for(wi.n)) {
         case 1:
@@ -143,13 +152,16 @@ __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int3
 }  // namespace
 
 // The pooled NPDU kernel: one persistent workgroup of W waves per CU (or two
-// of four), every wave one sector at a time.  The plan gave each workgroup
+// of four, twelve or sixteen), every wave one sector at a time.  The light
+// variant (LITE) holds only the narrow loop with coordinates from L2, so that
+// two workgroups of twelve or sixteen waves fit a CU's registers.  The plan gave each workgroup
 // its own sectors (the same for every round) in queues by page count; a
 // wave claims the next one under the workgroup's lock, entirely in LDS (the
 // claim counters of kRoundRing rounds at once and the page mask), so no
 // device-wide atomic is touched per sector: on MI355X those cross the XCDs.
-template <int W>
-__global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
+template <int W, bool LITE>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(LITE ? W / 2 : 1)))
+void pooled_npdu_kernel(const PoolArgs a) {
     static_assert(W <= kMaxPoolWaves, "seed table holds kMaxPoolWaves waves per workgroup");
     static_assert(kMaxLocalQueues == 64, "one queue per lane");
     extern __shared__ __attribute__((aligned(16))) uint32_t pool[];
@@ -333,7 +345,8 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
         const uint64_t take_rt = __builtin_amdgcn_s_memrealtime();
         const uint64_t take = __builtin_amdgcn_s_memtime();
         uint64_t loaded = take;
-        run_item<(W > 8 ? 16 : kLoadRound), (W <= 8)>(xyz_r, out_r, wu, pool + page * (kPoolPageBytes / 4), &loaded);
+        run_item<(W > 8 ? 16 : kLoadRound), (W <= 8), LITE>(xyz_r, out_r, wu, pool + page * (kPoolPageBytes / 4),
+                                                            &loaded);
         if (a.stamps) {
             const uint64_t end = __builtin_amdgcn_s_memtime();
             const uint64_t end_rt = __builtin_amdgcn_s_memrealtime();
@@ -400,11 +413,15 @@ __global__ __launch_bounds__(64 * W) void pooled_npdu_kernel(const PoolArgs a) {
 // Four or eight waves per workgroup load sectors 32 points per lane at a time
 // (at most two waves per SIMD fit their registers); twelve or sixteen (three
 // or four per SIMD) load 16 at a time, which keeps them within the registers.
+// The light twelve- and sixteen-wave kernels run two workgroups per CU (six
+// or eight waves per SIMD).
 void register_pool_variants(std::vector<PoolEntry>& v) {
-    v.push_back({4, (const void*)&pooled_npdu_kernel<4>});
-    v.push_back({8, (const void*)&pooled_npdu_kernel<8>});
-    v.push_back({12, (const void*)&pooled_npdu_kernel<12>});
-    v.push_back({16, (const void*)&pooled_npdu_kernel<16>});
+    v.push_back({4, false, (const void*)&pooled_npdu_kernel<4, false>});
+    v.push_back({8, false, (const void*)&pooled_npdu_kernel<8, false>});
+    v.push_back({12, false, (const void*)&pooled_npdu_kernel<12, false>});
+    v.push_back({16, false, (const void*)&pooled_npdu_kernel<16, false>});
+    v.push_back({12, true, (const void*)&pooled_npdu_kernel<12, true>});
+    v.push_back({16, true, (const void*)&pooled_npdu_kernel<16, true>});
 }
 
 }  // namespace afps

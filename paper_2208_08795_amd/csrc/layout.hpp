@@ -66,6 +66,12 @@ static_assert((kRoundRing & (kRoundRing - 1)) == 0, "ring slots by mask");
 // counters of kRoundRing rounds, round and exit words), bounded: the pool
 // takes the rest of the CU's LDS.
 constexpr int kPoolStaticLdsBytes = 2048;
+// LDS pages of each of `groups` pooled workgroups sharing a CU that holds
+// cu_pool_pages pages next to one workgroup's static LDS (each further
+// workgroup brings its own static LDS).
+constexpr int pool_pages_per_group(int cu_pool_pages, int groups) {
+    return (cu_pool_pages * kPoolPageBytes - (groups - 1) * kPoolStaticLdsBytes) / (groups * kPoolPageBytes);
+}
 constexpr int kSeedSleepCycles = 127 * 64;   // one s_sleep(127)
 
 // Whether a pooled NPDU sector keeps its coordinates in LDS, from its item flags.
@@ -77,6 +83,13 @@ constexpr int npdu_pool_pages(int n, bool xyz_in_lds) {
 }
 // Pages of the sector the built-in placement gives (coordinates in LDS up to 8192 points).
 constexpr int npdu_pool_pages(int n) { return npdu_pool_pages(n, npdu_r_for(n) <= 2); }
+// Sectors the light pooled kernels serve (the narrow loop with coordinates
+// read from L2 is all they hold, which keeps them small enough for six or
+// eight waves per SIMD): at most 4096 points, 0 <= k <= 64, coordinates out
+// of LDS.
+constexpr bool npdu_item_lite(int n, int k, int flags) {
+    return n <= 4096 && k >= 0 && k <= 64 && (flags & kItemXyzNotInLds) != 0;
+}
 
 // A pooled launch assigns every sector to one workgroup when the plan is
 // built (balanced by estimated cost), for every round alike.  Inside a

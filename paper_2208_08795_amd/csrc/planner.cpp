@@ -80,15 +80,20 @@ int32_t largest_sector(int32_t n, int32_t m) { return n / m + (n % m ? 1 : 0); }
 int32_t clamp_k(int32_t k, int32_t n_s) { return k > 2 * n_s ? 2 * n_s : k; }
 
 bool valid_pool_shape(int waves, int groups) {
-    return (waves == 4 && (groups == 1 || groups == 2)) || ((waves == 8 || waves == 12 || waves == 16) && groups == 1);
+    return (waves == 4 && (groups == 1 || groups == 2)) || ((waves == 8 || waves == 12 || waves == 16) && groups == 1) ||
+           ((waves == 12 || waves == 16) && groups == 2);
 }
+
+bool pool_shape_needs_lite(int waves, int groups) { return groups == 2 && waves >= 12; }
 
 bool npdu_xyz_in_lds(const PoolPolicy& policy, int n, int k) {
     if (npdu_r_for(n) > 2) return false;
     for (const auto& e : policy.placement)
         if (n <= e.n_max && k <= e.k_max) return e.xyz_in_lds != 0;
-    // built-in: registers for the sectors they serve best, else LDS
-    return !(n <= kRegsDefaultMaxPoints && k <= 64 && policy.waves <= 8);
+    // built-in: out of LDS (registers, or L2 in the 12- and 16-wave shapes)
+    // for the sectors the narrow loops serve, else LDS
+    (void)policy;
+    return !(n <= kRegsDefaultMaxPoints && k <= 64);
 }
 
 int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& env, PlanTables* out,
@@ -189,10 +194,12 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
     if (!npdu.empty()) {
         PlannedBucket bk{-1, 0, 0, 0, 0, 0, 0.0, 0.0};
         int max_pages = 0;
+        bool all_lite = true;
         for (const auto& st : npdu) {
             bk.cost += st.cost;
             bk.longest = std::max(bk.longest, st.cost);
             max_pages = std::max(max_pages, st.pages);
+            all_lite = all_lite && npdu_item_lite(st.item.n, st.item.k, st.item.flags);
         }
         bk.count = (int)npdu.size();
         // Waves per CU: one per SIMD keeps the longest sectors at full speed;
@@ -208,18 +215,20 @@ int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& en
         // runs as fast either way, but a launch then gives its LDS back half
         // a CU at a time, so a launch queued behind it on another stream
         // starts sooner.
-        plan.pool_groups = waves == 8 && max_pages <= plan.pool_pages / 2 ? 2 : 1;
+        plan.pool_groups = waves == 8 && max_pages <= pool_pages_per_group(plan.pool_pages, 2) ? 2 : 1;
         if (plan.pool_groups == 2) waves = 4;
         if (env.pool.waves > 0 && env.pool.groups > 0) {   // an explicit (tuned) shape
             const bool ok = valid_pool_shape(env.pool.waves, env.pool.groups) &&
-                            max_pages <= plan.pool_pages / env.pool.groups;
+                            max_pages <= pool_pages_per_group(plan.pool_pages, env.pool.groups) &&
+                            (all_lite || !pool_shape_needs_lite(env.pool.waves, env.pool.groups));
             if (ok) {
                 waves = env.pool.waves;
                 plan.pool_groups = env.pool.groups;
             }
         }
-        plan.pool_pages /= plan.pool_groups;
+        plan.pool_pages = pool_pages_per_group(plan.pool_pages, plan.pool_groups);
         plan.pool_waves = waves;
+        plan.pool_lite = pool_shape_needs_lite(waves, plan.pool_groups);   // all_lite holds then
         plan.seed_priority = std::max(0, std::min(3, env.pool.seed_priority));
         bk.block = 64 * waves;
         bk.lds_bytes = plan.pool_pages * kPoolPageBytes;

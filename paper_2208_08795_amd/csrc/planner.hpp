@@ -31,9 +31,9 @@ struct FullVariantInfo {
 // points and windows k <= k_max: LDS records (xyz_in_lds = 1) or outside LDS
 // (0: registers, or L2 where registers cannot serve).  The first entry
 // (ascending n_max, then k_max) that covers a sector decides; sectors no entry
-// covers hold their coordinates in registers up to kRegsDefaultMaxPoints
-// points with k <= 64 (in pooled shapes of at most 8 waves), else in LDS up
-// to 8192 points.
+// covers hold their coordinates out of LDS up to kRegsDefaultMaxPoints points
+// with k <= 64 (registers in pooled shapes of at most 8 waves, L2 in the
+// others), else in LDS up to 8192 points.
 struct NpduPlacement {
     int n_max, k_max, xyz_in_lds;
 };
@@ -80,6 +80,7 @@ struct PlanTables {
     int pool_pages = 0;                   // LDS pages of one pooled workgroup
     int pool_groups = 0;                  // pooled workgroups per CU (0 without NPDU sectors)
     int pool_waves = 0;                   // waves per pooled workgroup
+    bool pool_lite = false;               // the light kernel (two workgroups of 12 or 16 waves per CU)
     int seed_priority = 0;
     size_t ws_bytes = 0;
 };
@@ -93,8 +94,11 @@ int32_t largest_sector(int32_t n, int32_t m);
 // Windows wider than twice the sector behave exactly like 2 n_s.
 int32_t clamp_k(int32_t k, int32_t n_s);
 // Pooled launch shapes: one workgroup per CU of 4, 8, 12 or 16 waves (one to
-// four per SIMD), or two of 4 waves each owning half of the CU's pages.
+// four per SIMD), two of 4 waves each owning half of the CU's pages, or two
+// of 12 or 16 waves (six or eight per SIMD: light kernels, for plans whose
+// NPDU sectors all qualify, npdu_item_lite).
 bool valid_pool_shape(int waves, int groups);
+bool pool_shape_needs_lite(int waves, int groups);
 // Coordinates of an NPDU sector of n points with window k in LDS?
 bool npdu_xyz_in_lds(const PoolPolicy& policy, int n, int k);
 

@@ -74,6 +74,7 @@ struct PoolArgs {
 
 struct PoolEntry {
     int waves;
+    bool lite;   // only the narrow loop with coordinates from L2 (npdu_item_lite sectors)
     const void* kernel;
 };
 void register_pool_variants(std::vector<PoolEntry>& v);

@@ -54,8 +54,8 @@ PlannerEnv make_env(std::mt19937_64& rng, const std::vector<FakeVariant>& vars) 
     const float occ[] = {0.0f, 1.0f, 1.5f, 2.0f, 4.0f};
     env.pool.waves_per_simd = occ[std::uniform_int_distribution<int>(0, 4)(rng)];
     if (std::uniform_int_distribution<int>(0, 2)(rng) == 0) {
-        const int shapes[][2] = {{4, 1}, {8, 1}, {4, 2}, {8, 2}, {12, 1}, {16, 1}};
-        const auto& sh = shapes[std::uniform_int_distribution<int>(0, 5)(rng)];
+        const int shapes[][2] = {{4, 1}, {8, 1}, {4, 2}, {8, 2}, {12, 1}, {16, 1}, {12, 2}, {16, 2}};
+        const auto& sh = shapes[std::uniform_int_distribution<int>(0, 7)(rng)];
         env.pool.waves = sh[0];
         env.pool.groups = sh[1];
     }
@@ -173,6 +173,14 @@ void check_plan(const std::vector<afps_cloud_desc>& d, const PlannerEnv& env, co
             CHECK(bk.lds_bytes == t.pool_pages * kPoolPageBytes, "pool LDS");
             CHECK(t.pool_groups == 1 || t.pool_groups == 2, "pool groups");
             CHECK(t.pool_pages >= 1 && t.pool_pages * t.pool_groups <= env.cu_pool_pages, "pool pages");
+            // every workgroup of the shape fits one CU's LDS with its static part
+            CHECK(t.pool_groups * (t.pool_pages * kPoolPageBytes + kPoolStaticLdsBytes) <=
+                      env.cu_pool_pages * kPoolPageBytes + kPoolStaticLdsBytes, "pool LDS per CU");
+            bool all_lite = true;
+            for (int i = bk.first; i < bk.first + bk.count && i < (int)t.items.size(); ++i)
+                all_lite = all_lite && npdu_item_lite(t.items[i].n, t.items[i].k, t.items[i].flags);
+            CHECK(t.pool_lite == pool_shape_needs_lite(t.pool_waves, t.pool_groups), "light kernel choice");
+            CHECK(!t.pool_lite || all_lite, "light kernel with sectors it cannot serve");
             CHECK(bk.grid <= t.pool_groups * env.cu_count, "pool grid");
             CHECK(t.seed_priority >= 0 && t.seed_priority <= 3, "priority");
         }

@@ -391,13 +391,14 @@ def test_batch_of_256_every_cloud(B, torch_dev, occupancy):
         assert (plan.pool_waves, plan.pool_groups) == (4, 2)
 
 
-@pytest.mark.parametrize("n,groups", [(4992, 2), (4993, 1), (20160, 2), (20161, 1)])
+@pytest.mark.parametrize("n,groups", [(4928, 2), (4929, 1), (19904, 2), (19905, 1)])
 def test_split_pool_at_the_half_boundary(B, torch_dev, n, groups):
     """At two waves per SIMD the plan splits each CU into two workgroups when
-    its largest sector fits half of a CU's 159 pages: 4992 points of 16-byte
-    records take 79 pages (78 blocks and the padding block), 4993 take 80;
-    20160 points of distance-only records take 79 (316 blocks of 256 bytes),
-    20161 take 80.  Either way every index is exact."""
+    its largest sector fits one of them: a CU's 158 pages less the second
+    workgroup's static LDS leave 78 each.  4928 points of 16-byte records take
+    78 pages (77 blocks and the padding block), 4929 take 79; 19904 points of
+    distance-only records take 78 (312 blocks of 256 bytes), 19905 take 79.
+    Either way every index is exact."""
     torch, dev = torch_dev
     clouds = [synth.object_cloud(n, seed=n), synth.object_cloud(3000, seed=1), synth.object_cloud(700, seed=2)]
     sizes, cs = [len(p) for p in clouds], [600, 500, 175]
@@ -597,11 +598,14 @@ def test_pooled_sectors_with_tuned_coordinate_placement(B, torch_dev, placement,
         B.tune_reset()
 
 
-@pytest.mark.parametrize("shape", [(4, 1), (8, 1), (4, 2), (12, 1), (16, 1)])
+@pytest.mark.parametrize("shape", [(4, 1), (8, 1), (4, 2), (12, 1), (16, 1), (12, 2), (16, 2)])
 @pytest.mark.parametrize("seeding", [(False, 0), (True, 3)])
 def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
     """Every pooled launch shape and seeding policy the tuner can pick, on
-    uneven clouds of the batch workload: indices equal the oracle's."""
+    uneven clouds of the batch workload (sectors of at most 4096 points, k =
+    32: the two-workgroup 12- and 16-wave shapes run the light kernels), and
+    the light shapes once more with every reading on ragged clouds: indices
+    equal the oracle's."""
     torch, dev = torch_dev
     clouds = synth.batch_of_objects(40, seed=21, n_min=1024, n_max=32768)
     cs = [len(p) // 4 for p in clouds]
@@ -609,6 +613,15 @@ def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
     try:
         plan = _batch_case(B, torch, dev, clouds, cs, [8] * 40, [32] * 40, [0] * 40, graph_replays=1)
         assert (plan.pool_waves, plan.pool_groups) == shape
+        if shape[1] == 2 and shape[0] >= 12:
+            sizes = [4096, 4095, 2049, 777, 65, 1, 300, 3000]
+            ks = [64, 32, 63, 0, 64, 0, 7, 33]
+            flags = [0, 1, 2, 3, 0, 2, 1, 0]
+            cl = [synth.object_cloud(n, seed=i) if n >= 64 else synth.uniform_cube(n, seed=i)
+                  for i, n in enumerate(sizes)]
+            plan = _batch_case(B, torch, dev, cl, [max(1, n // 3) for n in sizes], [1] * 8, ks,
+                               [n // 2 for n in sizes], graph_replays=1, flags=flags)
+            assert (plan.pool_waves, plan.pool_groups) == shape
     finally:
         B.tune_reset()
 
