@@ -541,7 +541,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving streams")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuners (built-in rules)")
     ap.add_argument("--pool", type=str, default=None,
-                    help="pooled launch shape 'waves,groups' for the timed batch (skips its tuning)")
+                    help="pooled launch policy 'waves,groups[,seed_sleep,seed_priority]' for the timed batch "
+                         "(skips its tuning; seeding defaults to 1,3)")
     ap.add_argument("--regs-up-to", type=int, default=None,
                     help="NPDU sectors of at most this many points hold their coordinates out of LDS "
                          "(registers), larger ones in LDS (with --pool; 0 = all in LDS)")
@@ -579,8 +580,12 @@ def main():
 
     res_tune = None
     if args.pool is not None:
-        w, g = (int(x) for x in args.pool.split(","))
-        binding.set_pool_policy(w, g, True, 3)
+        pol = [int(x) for x in args.pool.split(",")]
+        if len(pol) not in (2, 4):
+            ap.error("--pool takes waves,groups or waves,groups,seed_sleep,seed_priority")
+        w, g = pol[:2]
+        sleep, prio = (pol[2], pol[3]) if len(pol) == 4 else (1, 3)
+        binding.set_pool_policy(w, g, bool(sleep), prio)
         if args.regs_up_to is not None:
             if args.regs_up_to:
                 binding.tune_npdu(args.regs_up_to, K, False)
@@ -667,7 +672,7 @@ def main():
     # (D only) with the coordinates in registers
     lds_round = 20 * cnt["updates_records"] + 8 * (cnt["updates"] - cnt["updates_records"])
     lds_peak_tbs = CUS * LDS_BYTES_PER_CLK_PER_CU * clock_ghz * 1e9 / 1e12
-    rec = counter_record("%s, registers up to %d" % (label, regs_up_to))
+    rec = counter_record("%s, coordinates out of LDS up to %d" % (label, regs_up_to))
     roof = {"bound": "alu", "kernel": label, "achieved": ops_launch / launch_s / 1e12, "peak": VALU_PEAK_TOPS,
             "unit": "TOPS (fp32 VALU lane-ops)", "frac": ops_launch / launch_s / 1e12 / VALU_PEAK_TOPS,
             "traffic": (int(rec["traffic_bytes_per_round"] * steps) if rec and rec.get("traffic_bytes_per_round")

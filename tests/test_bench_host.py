@@ -42,7 +42,7 @@ def test_fps_ops():
 
 def test_counter_record_follows_the_source_hash():
     if not os.path.exists(RECORD):
-        assert bench.counter_record("pooled_npdu_kernel<8>, registers up to 4096") is None
+        assert bench.counter_record("pooled_npdu_kernel<16>, coordinates out of LDS up to 4096") is None
         return
     with open(RECORD) as f:
         rec = json.load(f)
