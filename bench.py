@@ -714,14 +714,31 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
-    # ---- one step's own latency (one pass at a time, graph replays)
+    # ---- one step's own latency (one pass at a time, graph replays): the
+    # throughput-tuned plan, then the built-in policy (coordinates in LDS
+    # records: the shortest single launch), which the rest of the run (serving
+    # included) keeps as the latency operating point
+    reps = max(20, min(steps, 100))
     plan.launch(xyz_all, out_all=ref, graph=True, stream=stream)
     torch.cuda.synchronize()
-    ev_ms = _event_ms(torch, lambda: plan.launch(xyz_all, out_all=ref, graph=True, stream=stream), stream,
-                      max(20, min(steps, 100)))
+    ev_tuned = _event_ms(torch, lambda: plan.launch(xyz_all, out_all=ref, graph=True, stream=stream), stream, reps)
+    binding.tune_npdu_clear()
+    binding.set_pool_policy(0, 0, True, 3)
+    lplan = binding.BatchPlan(sizes, cs, [M] * 256, [K] * 256, [0] * 256, device=dev)
+    lout = lplan.launch(xyz_all, stream=stream, graph=True)
+    torch.cuda.synchronize()
+    if not torch.equal(lout, ref):
+        raise SystemExit("bench: the built-in policy's indices differ from the tuned plan's")
+    ev_ms = _event_ms(torch, lambda: lplan.launch(xyz_all, out_all=lout, graph=True, stream=stream), stream, reps)
     res["batch_latency"] = {"unit": "ms", "what": "one step alone (the whole batch of 256 clouds, one pooled "
-                                                  "launch per step, graph replays one at a time), HIP events",
-                            "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99)}
+                                                  "launch per step, graph replays one at a time), HIP events, "
+                                                  "built-in policy (pooled_npdu_kernel<%d>, coordinates in LDS "
+                                                  "records): the latency operating point, kept for the rest of "
+                                                  "the run" % lplan.pool_waves,
+                            "p50": percentile(ev_ms, 50), "p99": percentile(ev_ms, 99),
+                            "throughput_policy": {"kernel": label, "p50": percentile(ev_tuned, 50),
+                                                  "p99": percentile(ev_tuned, 99)}}
+    lplan.close()
 
     if not args.no_tune:
         log("autotuning full-update variants")

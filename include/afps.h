@@ -339,9 +339,10 @@ void afps_tune_reset(void);   /* forgets every tuned entry and the pool policy (
  * registers for sectors of at most 4096 points with k <= 64 in pooled
  * launches of at most 8 waves per workgroup, else they are read from L2).
  * The entry with the smallest n_s_max (then k_max) that covers a sector
- * decides; without one, sectors of at most 4096 points with k <= 64 hold
- * their coordinates out of LDS (registers in pooled launches of at most 8
- * waves per workgroup, else L2) and other sectors up to 8192 points in LDS.  Read from
+ * decides; without one, sectors up to 8192 points keep their coordinates in
+ * LDS (the fastest iteration: the shortest single launch).  Batches bound by
+ * throughput gain from placements out of LDS (autotune.tune_npdu), which let
+ * a CU run more sectors at once.  Read from
  * AFPS_TUNE_CACHE as lines "npdu n_s_max k_max xyz_in_lds".  AFPS_ERR_ARG
  * for bad values.  afps_npdu_xyz_in_lds reports the placement a sector would
  * get.

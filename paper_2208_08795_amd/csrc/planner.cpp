@@ -90,10 +90,11 @@ bool npdu_xyz_in_lds(const PoolPolicy& policy, int n, int k) {
     if (npdu_r_for(n) > 2) return false;
     for (const auto& e : policy.placement)
         if (n <= e.n_max && k <= e.k_max) return e.xyz_in_lds != 0;
-    // built-in: out of LDS (registers, or L2 in the 12- and 16-wave shapes)
-    // for the sectors the narrow loops serve, else LDS
-    (void)policy;
-    return !(n <= kRegsDefaultMaxPoints && k <= 64);
+    // built-in: 16-byte records in LDS (the fastest iteration, so the
+    // shortest single launch); throughput-bound batches tune a placement out
+    // of LDS (registers or L2), which lets a CU hold more sectors at once
+    (void)k;
+    return true;
 }
 
 int build_plan(const afps_cloud_desc* descs, int32_t batch, const PlannerEnv& env, PlanTables* out,

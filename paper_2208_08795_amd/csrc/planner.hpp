@@ -29,15 +29,13 @@ struct FullVariantInfo {
 
 // Where an NPDU sector's coordinates live, for sectors of at most n_max
 // points and windows k <= k_max: LDS records (xyz_in_lds = 1) or outside LDS
-// (0: registers, or L2 where registers cannot serve).  The first entry
-// (ascending n_max, then k_max) that covers a sector decides; sectors no entry
-// covers hold their coordinates out of LDS up to kRegsDefaultMaxPoints points
-// with k <= 64 (registers in pooled shapes of at most 8 waves, L2 in the
-// others), else in LDS up to 8192 points.
+// (0: registers in pooled shapes of at most 8 waves for sectors of at most
+// 4096 points with k <= 64, else L2).  The first entry (ascending n_max, then
+// k_max) that covers a sector decides; sectors no entry covers keep their
+// coordinates in LDS up to 8192 points.
 struct NpduPlacement {
     int n_max, k_max, xyz_in_lds;
 };
-constexpr int kRegsDefaultMaxPoints = 4096;
 
 // Tunable policy of the pooled NPDU launch.
 struct PoolPolicy {

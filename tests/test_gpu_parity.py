@@ -610,6 +610,8 @@ def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
     clouds = synth.batch_of_objects(40, seed=21, n_min=1024, n_max=32768)
     cs = [len(p) // 4 for p in clouds]
     B.set_pool_policy(shape[0], shape[1], seeding[0], seeding[1])
+    if shape[1] == 2 and shape[0] >= 12:   # the light kernels serve sectors with coordinates out of LDS
+        B.tune_npdu(4096, 64, False)
     try:
         plan = _batch_case(B, torch, dev, clouds, cs, [8] * 40, [32] * 40, [0] * 40, graph_replays=1)
         assert (plan.pool_waves, plan.pool_groups) == shape
