@@ -154,11 +154,12 @@ __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int3
 // The pooled NPDU kernel: one persistent workgroup of W waves per CU (or two
 // of four, twelve or sixteen), every wave one sector at a time.  The light
 // variant (LITE) holds only the narrow loop with coordinates from L2, so that
-// two workgroups of twelve or sixteen waves fit a CU's registers.  The plan gave each workgroup
-// its own sectors (the same for every round) in queues by page count; a
-// wave claims the next one under the workgroup's lock, entirely in LDS (the
-// claim counters of kRoundRing rounds at once and the page mask), so no
-// device-wide atomic is touched per sector: on MI355X those cross the XCDs.
+// two workgroups of twelve or sixteen waves fit a CU's registers.  The plan
+// gave each workgroup its own sectors (the same for every round) in queues
+// by page count; a wave claims the next one under the workgroup's lock,
+// entirely in LDS (the claim counters of kRoundRing rounds at once and the
+// page mask), so no device-wide atomic is touched per sector: on MI355X
+// those cross the XCDs.
 template <int W, bool LITE>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(LITE ? W / 2 : 1)))
 void pooled_npdu_kernel(const PoolArgs a) {

@@ -107,12 +107,38 @@ def test_stamped_launch_is_exact_and_its_stamps_are_consistent(env, batch256):
     plan.close()
 
 
-def test_rounds_in_one_launch_equal_separate_launches(env):
+# Pooled launch policies of the launches of several rounds: the built-in one
+# (coordinates in LDS records), registers at 8 waves per CU, L2 at 16, and the
+# light kernel of two 16-wave workgroups per CU.
+ROUND_POLICIES = {"builtin": None, "regs_8": (8, 1), "l2_16": (16, 1), "lite_16x2": (16, 2)}
+
+
+def _set_round_policy(B, name):
+    B.tune_npdu_clear()
+    shape = ROUND_POLICIES[name]
+    if shape is not None:
+        B.set_pool_policy(shape[0], shape[1], True, 3)
+        B.tune_npdu(4096, 64, False)
+    return shape
+
+
+@pytest.mark.parametrize("policy", list(ROUND_POLICIES))
+def test_rounds_in_one_launch_equal_separate_launches(env, policy):
     """Several rounds of one plan in one pooled launch, alternating two inputs
     of the same layout, every round writing its own output: each round equals
     a separate launch of the plan on that input (and the oracle on samples);
-    one round equals afps_plan_launch; a graph capture replays exactly."""
+    one round equals afps_plan_launch; a graph capture replays exactly; under
+    every pooled policy (placements in LDS, registers and L2, the light
+    kernel)."""
     torch, B, dev = env
+    shape = _set_round_policy(B, policy)
+    try:
+        _rounds_case(torch, B, dev, shape)
+    finally:
+        B.tune_npdu_clear()
+
+
+def _rounds_case(torch, B, dev, shape):
     sizes = [int(n) for n in np.exp(np.random.default_rng(4).uniform(np.log(1024), np.log(32768), 48)).round()]
     cs = [n // 4 for n in sizes]
     inputs = []
@@ -120,6 +146,8 @@ def test_rounds_in_one_launch_equal_separate_launches(env):
         clouds = [synth.object_cloud(n, seed=1000 * seed + i) for i, n in enumerate(sizes)]
         inputs.append((clouds, torch.from_numpy(np.concatenate(clouds)).to(dev)))
     plan = B.BatchPlan(sizes, cs, [8] * 48, [32] * 48, [0] * 48, device=dev)
+    if shape is not None:
+        assert (plan.pool_waves, plan.pool_groups) == shape
     want = []
     for clouds, xyz in inputs:
         want.append(plan.launch(xyz).clone())
@@ -159,15 +187,22 @@ def test_rounds_in_one_launch_equal_separate_launches(env):
     plan.close()
 
 
-def test_rounds_forced_timeouts_fail_whole_sectors(env):
+@pytest.mark.parametrize("policy", list(ROUND_POLICIES))
+def test_rounds_forced_timeouts_fail_whole_sectors(env, policy):
     """A spin limit of 1 in a launch of several rounds: every sector of every
     round is exact or entirely -1, the plan reports the failure, and the next
-    launch of several rounds is exact again."""
+    launch of several rounds is exact again; under every pooled policy."""
     torch, B, dev = env
     clouds = synth.batch_of_objects(64, seed=9, n_min=2048, n_max=32768)
     sizes, cs = [len(p) for p in clouds], [len(p) // 4 for p in clouds]
     xyz = torch.from_numpy(np.concatenate(clouds)).to(dev)
-    plan = B.BatchPlan(sizes, cs, [8] * 64, [32] * 64, [0] * 64, device=dev)
+    shape = _set_round_policy(B, policy)
+    try:
+        plan = B.BatchPlan(sizes, cs, [8] * 64, [32] * 64, [0] * 64, device=dev)
+    finally:
+        B.tune_npdu_clear()
+    if shape is not None:
+        assert (plan.pool_waves, plan.pool_groups) == shape
     want = plan.launch(xyz).clone().cpu().numpy()
     outs = [torch.full((plan.total_samples,), -7, dtype=torch.int32, device=dev) for _ in range(3)]
     table = plan.round_table([(xyz, o) for o in outs])
