@@ -580,11 +580,14 @@ __device__ __forceinline__ void sample_sector_npdu_narrow_l2(const float* __rest
         }
     }
 
-    // The window [lo, hi] of sample j.
-    auto window = [&](int j, int& lo, int& hi) {
+    auto step = [&](int s) {
+        // the sample's coordinates: one wave-uniform load at a 32-bit offset
+        const float* const p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(xyz) + (uint32_t)(12 * cur));
+        const float px = p[0], py = p[1], pz = p[2];
+        int lo, hi;
         if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
-            lo = j - below;
-            hi = j + above;
+            lo = cur - below;
+            hi = cur + above;
             if (lo < 0) {
                 hi -= lo;
                 lo = 0;
@@ -594,52 +597,18 @@ __device__ __forceinline__ void sample_sector_npdu_narrow_l2(const float* __rest
                 hi = n - 1;
             }
         } else {
-            lo = max(0, j - below);
-            hi = min(n - 1, j + above);
+            lo = max(0, cur - below);
+            hi = min(n - 1, cur + above);
         }
-    };
-    // Prefetch: the next sample is most often the lowest index holding the
-    // maximum of the blocks outside the current window (known before the
-    // window is updated), so the loads of that sample's window are issued
-    // one iteration early; an iteration whose sample is the predicted one
-    // uses them, any other loads its own.  Predicted indices may lie past the
-    // sector: every load goes through the bounded buffer resource.
-    int pf_cur = -1;   // the predicted sample
-    v3u32 pfA = {0u, 0u, 0u}, pfB = {0u, 0u, 0u}, pfP = {0u, 0u, 0u};
-    auto load_window = [&](int j, v3u32& A, v3u32& B, v3u32& P) {
-        int lo, hi;
-        window(j, lo, hi);
-        const int off = 768 * (lo >> 6) + lane12;   // block lo/64 + 1 at 768 bytes further
-        A = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off, 0, 0);
-        B = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off + 768, 0, 0);
-        P = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, 12 * j, 0, 0);
-    };
-
-    auto step = [&](int s) {
-        int lo, hi;
-        window(cur, lo, hi);
         const int blo = lo >> 6;
-        v3u32 A, B, P;
-        if (cur == pf_cur) {
-            A = pfA;
-            B = pfB;
-            P = pfP;
-        } else {
-            load_window(cur, A, B, P);
-        }
+        const int off = 768 * blo + lane12;   // block blo + 1 at 768 bytes further
+        const v3u32 A = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off, 0, 0);
+        const v3u32 B = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off + 768, 0, 0);
         uint32_t* const wb = rec_lane + 64 * blo;
         const uint32_t da = wb[0], db = wb[64];
 
-        const uint32_t outside = (uint32_t)(lane - blo) > 1u ? bm : 0u;
-        const uint32_t g_out = wave_max(outside);
-        {
-            const int wp = (int)__builtin_ctzll(ballot(outside == g_out));
-            pf_cur = __builtin_amdgcn_readfirstlane(64 * wp + (int)readlane(bi, wp));
-            load_window(pf_cur, pfA, pfB, pfP);
-            __builtin_amdgcn_sched_barrier(0);   // issued before this iteration waits for its own loads
-        }
+        const uint32_t g_out = wave_max((uint32_t)(lane - blo) > 1u ? bm : 0u);
 
-        const float px = __uint_as_float(P.x), py = __uint_as_float(P.y), pz = __uint_as_float(P.z);
         const int t = lane - (lo & 63);
         const int span = hi - lo;
         const uint32_t e0 = min(da, sq_dist_bits(__uint_as_float(A.x), __uint_as_float(A.y), __uint_as_float(A.z),
