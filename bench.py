@@ -8,7 +8,9 @@ batches processed back to back on the device; the rounds alternate over two
 resident copies of the input and each writes its own output), bracketed by
 synchronisations; the same launch's HIP-event duration is the roofline's time
 basis, so `value` and `roofline` share one clock.  Inputs are resident in HBM
-before the timed region.  The same 256 clouds are also sampled with plain FPS.
+before the timed region, and untimed launches of the same shape run back to
+back for --settle-ms right before it (a GPU coming out of idle needs tens of ms
+of load to reach its steady clocks).  The same 256 clouds are also sampled with plain FPS.
 
 Prints ONE JSON line (rank 0, N = 1).  Extra fields: one step's own latency,
 device-measured cycles per iteration (per-sector timestamps), plain-FPS
@@ -546,6 +548,9 @@ def main():
     ap.add_argument("--regs-up-to", type=int, default=None,
                     help="NPDU sectors of at most this many points hold their coordinates out of LDS "
                          "(registers), larger ones in LDS (with --pool; 0 = all in LDS)")
+    ap.add_argument("--settle-ms", type=float, default=50.0,
+                    help="untimed launches of the timed launch's shape, back to back right before it, for at "
+                         "least this long (0: none)")
     ap.add_argument("--only-timed", action="store_true",
                     help="stop after the timed launch (for profiler runs: warm-up and timed launches only)")
     args = ap.parse_args()
@@ -553,8 +558,8 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(independent clouds would shard by request with no exchange)", file=sys.stderr)
         sys.exit(2)
-    if args.steps < 1 or args.steps > 4096 or args.warmup < 0:
-        ap.error("--steps must be in [1, 4096] (rounds of one launch) and --warmup >= 0")
+    if args.steps < 1 or args.steps > 4096 or args.warmup < 0 or args.settle_ms < 0:
+        ap.error("--steps must be in [1, 4096] (rounds of one launch), --warmup and --settle-ms >= 0")
 
     import torch
     from paper_2208_08795_amd import autotune, binding, synth
@@ -619,6 +624,26 @@ def main():
         torch.cuda.synchronize()
         if not torch.equal(single, ref):
             raise SystemExit("bench: a round's indices differ from a single pass")
+    # The GPU's clocks settle only after tens of ms of continuous load (a
+    # launch that starts from idle runs its first ~20 ms up to 10% slower), so
+    # launches of the timed launch's own shape (K rounds, their own outputs)
+    # run back to back, untimed, right before it: the timed launch then
+    # measures the steady state of a stream of batches.
+    settle = None
+    if args.settle_ms > 0:
+        souts = torch.full((steps, plan.total_samples), -7, dtype=torch.int32, device=dev)
+        stable = plan.round_table([(inputs[r % 2], souts[r]) for r in range(steps)])
+        torch.cuda.synchronize()
+        ts, n_settle = time.perf_counter(), 0
+        while n_settle == 0 or time.perf_counter() - ts < args.settle_ms / 1e3:
+            plan.launch_rounds(stable, stream=stream)
+            torch.cuda.synchronize()
+            n_settle += 1
+        settle = {"launches": n_settle, "rounds": n_settle * steps,
+                  "ms": round((time.perf_counter() - ts) * 1e3, 2),
+                  "what": "untimed launches of K rounds (the timed launch's shape, outputs of their own, checked "
+                          "after the timed launch), back to back right before it, so that the timed launch starts "
+                          "at the clocks of continuous load"}
     ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev_a.record(stream)
@@ -631,6 +656,10 @@ def main():
     plan.status(stream=stream)
     if not bool((outs == ref.unsqueeze(0)).all()):
         raise SystemExit("bench: a timed round's indices differ from the warm-up's")
+    if settle is not None:
+        if not bool((souts == ref.unsqueeze(0)).all()):
+            raise SystemExit("bench: a settling round's indices differ from the warm-up's")
+        del souts, stable
     ms_per_step = wall * 1e3 / steps
     value = total_samples * steps / wall
     log("AFPS-NPDU: %d rounds in one launch, %.4f ms/step (launch %.3f ms), %.3e sampled pts/s" %
@@ -653,6 +682,7 @@ def main():
                               "seconds": round(res_tune["seconds"], 2),
                               "what": "ms per batch in one launch of 20 rounds, per pooled launch shape "
                                       "(waves, workgroups per CU), bound of coordinates out of LDS and seeding (sleep, priority)"}
+    res["settle"] = settle
     res["sclk_mhz_after_timed_steps"] = sclk
 
     # ---- roofline of the dominant kernel, on the timed launch's own time
