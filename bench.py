@@ -58,8 +58,12 @@ VALU_CYCLES_PER_INST = 4
 # of the window's distances (1024 + 2 x 1024 + 512 bytes of lanes in 4
 # instructions).  Coordinates in registers: one paired 4-byte read and one
 # paired 4-byte write of the window's distances (512 + 512 in 2).
+# Coordinates from L2 with windows of at most 64 points: a 4-byte read and
+# write of the window's own lanes and a paired 4-byte read of the two blocks
+# holding it (256 + 256 + 512 in 3).
 LDS_BYTES_PER_INST_RECORDS = (1024 + 2 * 1024 + 512) / 4
 LDS_BYTES_PER_INST_REGS = (512 + 512) / 2
+LDS_BYTES_PER_INST_L2_WINDOW = (256 + 256 + 512) / 3
 
 
 def log(msg):
@@ -726,7 +730,10 @@ def main():
     if rec:
         valu = rec["SQ_INSTS_VALU_per_round"]
         roof["valu_issue_frac"] = valu * VALU_CYCLES_PER_INST / (CUS * SIMDS_PER_CU * round_s * clock_ghz * 1e9)
-        per_inst = LDS_BYTES_PER_INST_REGS if cnt["updates_records"] == 0 else LDS_BYTES_PER_INST_RECORDS
+        if cnt["updates_records"]:
+            per_inst = LDS_BYTES_PER_INST_RECORDS
+        else:   # the 4- and 8-wave kernels hold coordinates out of LDS in registers, the others read L2
+            per_inst = LDS_BYTES_PER_INST_REGS if plan.pool_waves <= 8 or K > 63 else LDS_BYTES_PER_INST_L2_WINDOW
         kb = rec["SQ_INSTS_LDS_per_round"] * per_inst
         roof["lds"].update({"kernel_bytes_per_launch": kb * steps, "kernel_frac": kb / round_s / 1e12 / lds_peak_tbs})
         roof["counters_per_round"] = {k: v for k, v in rec.items() if k.endswith("_per_round")}

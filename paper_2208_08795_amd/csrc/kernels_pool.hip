@@ -102,6 +102,28 @@ __device__ __forceinline__ T* global_ptr(int64_t bits) {
 // (REGS: kernels of at most two waves per SIMD, sectors of at most 4096
 // points, k <= 64), else they are read from L2 (by the narrow loop for such
 // sectors without REGS).
+// The narrow loop with coordinates from L2 (k <= 64): windows of at most 64
+// points (k <= 63) update their own 64 lanes, the widest its two blocks.
+__device__ __forceinline__ void run_narrow_l2(const float* __restrict__ xyz, int32_t* __restrict__ out,
+                                              const WorkItem& wi, int f, uint32_t* lds, uint64_t* t_loaded) {
+    const bool first_full = (f & kNpduFirstFull) != 0;
+    if (wi.k <= 63) {
+        if (f & kNpduShiftEdges)
+            sample_sector_npdu_narrow_l2<true, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, first_full,
+                                                     t_loaded);
+        else
+            sample_sector_npdu_narrow_l2<false, true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, first_full,
+                                                      t_loaded);
+    } else {
+        if (f & kNpduShiftEdges)
+            sample_sector_npdu_narrow_l2<true, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, first_full,
+                                                      t_loaded);
+        else
+            sample_sector_npdu_narrow_l2<false, false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, first_full,
+                                                       t_loaded);
+    }
+}
+
 template <int LR, bool REGS, bool LITE>
 __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int32_t* __restrict__ out_all,
                                          const WorkItem& wi, uint32_t* lds, uint64_t* t_loaded) {
@@ -109,12 +131,7 @@ __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int3
     int32_t* out = out_all + wi.out_offset;
     const int f = wi.flags & ~kItemXyzNotInLds;
     if constexpr (LITE) {   // the plan holds npdu_item_lite sectors only
-        if (f & kNpduShiftEdges)
-            sample_sector_npdu_narrow_l2<true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
-                                               (f & kNpduFirstFull) != 0, t_loaded);
-        else
-            sample_sector_npdu_narrow_l2<false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
-                                                (f & kNpduFirstFull) != 0, t_loaded);
+        run_narrow_l2(xyz, out, wi, f, lds, t_loaded);
         return;
     }
     const bool in_lds = npdu_item_xyz_in_lds(wi.n, wi.flags);
@@ -130,12 +147,7 @@ __device__ __forceinline__ void run_item(const float* __restrict__ xyz_all, int3
                     sample_sector_npdu_regs<false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
                                                    (f & kNpduFirstFull) != 0, t_loaded);
             } else if (wi.k <= 64) {
-                if (f & kNpduShiftEdges)
-                    sample_sector_npdu_narrow_l2<true>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
-                                                       (f & kNpduFirstFull) != 0, t_loaded);
-                else
-                    sample_sector_npdu_narrow_l2<false>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds,
-                                                        (f & kNpduFirstFull) != 0, t_loaded);
+                run_narrow_l2(xyz, out, wi, f, lds, t_loaded);
             } else {
                 sample_sector_npdu<1, false, LR>(xyz, wi.n, wi.c, wi.k, wi.start, wi.base, out, lds, f, t_loaded);
             }

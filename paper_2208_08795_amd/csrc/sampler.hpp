@@ -525,12 +525,16 @@ __device__ __forceinline__ void sample_sector_npdu_narrow(const float* __restric
 // global memory (L2) and only D in LDS (npdu_lds_words(n, false) words):
 //   n <= 4096, k <= 64.
 // The loop of sample_sector_npdu_narrow with its three LDS record reads
-// replaced by loads: the sample's 12 bytes (one wave-uniform load) and the
-// two window blocks' (one 12-byte load per lane each, through a buffer
-// resource bounded to the sector, so the padding block reads zeros).  The
-// memory round trip is on every iteration's path, which many waves per SIMD
-// hide; the sector takes a quarter of the LDS of 16-byte records.
-template <bool SHIFT>
+// replaced by loads through a buffer resource bounded to the sector (points
+// past it read as zeros): the sample's 12 bytes (one wave-uniform load) and
+// the window's.  With WIN (windows of at most 64 points, k <= 63) lane l
+// holds point lo + l: one 12-byte load per lane, the update of D written to
+// LDS and the two blocks holding the window read back for their maxima; else
+// (k = 64) the two blocks are loaded and updated in place, 128 lanes for at
+// most 65 points.  The memory round trip is on every iteration's path, which
+// many waves per SIMD hide; the sector takes a quarter of the LDS of 16-byte
+// records.
+template <bool SHIFT, bool WIN>
 __device__ __forceinline__ void sample_sector_npdu_narrow_l2(const float* __restrict__ xyz, int n, int c, int k,
                                                              int cur, int base, int32_t* __restrict__ out,
                                                              uint32_t* lds, bool first_full, uint64_t* t_loaded) {
@@ -601,24 +605,40 @@ __device__ __forceinline__ void sample_sector_npdu_narrow_l2(const float* __rest
             hi = min(n - 1, cur + above);
         }
         const int blo = lo >> 6;
-        const int off = 768 * blo + lane12;   // block blo + 1 at 768 bytes further
-        const v3u32 A = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off, 0, 0);
-        const v3u32 B = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off + 768, 0, 0);
-        uint32_t* const wb = rec_lane + 64 * blo;
-        const uint32_t da = wb[0], db = wb[64];
-
-        const uint32_t g_out = wave_max((uint32_t)(lane - blo) > 1u ? bm : 0u);
-
-        const int t = lane - (lo & 63);
         const int span = hi - lo;
-        const uint32_t e0 = min(da, sq_dist_bits(__uint_as_float(A.x), __uint_as_float(A.y), __uint_as_float(A.z),
-                                                 px, py, pz));
-        const uint32_t e1 = min(db, sq_dist_bits(__uint_as_float(B.x), __uint_as_float(B.y), __uint_as_float(B.z),
-                                                 px, py, pz));
-        const uint32_t d0 = (uint32_t)t <= (uint32_t)span ? e0 : da;
-        const uint32_t d1 = t <= span - 64 ? e1 : db;
-        wb[0] = d0;
-        wb[64] = d1;
+        uint32_t* const wb = rec_lane + 64 * blo;
+        uint32_t d0, d1, g_out;
+        if constexpr (WIN) {
+            // The window's own 64 lanes (point lo + lane; the window ends at
+            // lane span <= 63): one load, one update, written to LDS, and the
+            // two blocks holding it read back for their maxima.
+            const v3u32 P = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, 12 * lo + lane12, 0, 0);
+            uint32_t* const ww = rec_lane + lo;
+            const uint32_t dw = ww[0];
+            g_out = wave_max((uint32_t)(lane - blo) > 1u ? bm : 0u);
+            const uint32_t ew = min(dw, sq_dist_bits(__uint_as_float(P.x), __uint_as_float(P.y),
+                                                     __uint_as_float(P.z), px, py, pz));
+            ww[0] = lane <= span ? ew : dw;
+            d0 = wb[0];
+            d1 = wb[64];
+        } else {
+            const int off = 768 * blo + lane12;   // block blo + 1 at 768 bytes further
+            const v3u32 A = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off, 0, 0);
+            const v3u32 B = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, off + 768, 0, 0);
+            const uint32_t da = wb[0], db = wb[64];
+
+            g_out = wave_max((uint32_t)(lane - blo) > 1u ? bm : 0u);
+
+            const int t = lane - (lo & 63);
+            const uint32_t e0 = min(da, sq_dist_bits(__uint_as_float(A.x), __uint_as_float(A.y),
+                                                     __uint_as_float(A.z), px, py, pz));
+            const uint32_t e1 = min(db, sq_dist_bits(__uint_as_float(B.x), __uint_as_float(B.y),
+                                                     __uint_as_float(B.z), px, py, pz));
+            d0 = (uint32_t)t <= (uint32_t)span ? e0 : da;
+            d1 = t <= span - 64 ? e1 : db;
+            wb[0] = d0;
+            wb[64] = d1;
+        }
 
         uint32_t g0, g1;
         wave_max2(d0, d1, g0, g1);
