@@ -585,8 +585,10 @@ __device__ __forceinline__ void sample_sector_npdu_narrow_l2(const float* __rest
     }
 
     auto step = [&](int s) {
-        // the sample's coordinates: one wave-uniform load at a 32-bit offset
-        const float* const p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(xyz) + (uint32_t)(12 * cur));
+        // the sample's coordinates: scalar loads (the points are read-only
+        // while the kernel runs, so the constant address space holds)
+        typedef const __attribute__((address_space(4))) float* ConstPtr;
+        const ConstPtr p = (ConstPtr)xyz + 3 * cur;
         const float px = p[0], py = p[1], pz = p[2];
         int lo, hi;
         if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
