@@ -598,6 +598,34 @@ def test_pooled_sectors_with_tuned_coordinate_placement(B, torch_dev, placement,
         B.tune_reset()
 
 
+@pytest.mark.parametrize("shape", [(16, 1), (12, 2)])
+def test_l2_window_update_edges(B, torch_dev, shape):
+    """The narrow loop with coordinates from L2 (D alone in LDS): windows of
+    at most 64 points update the 64 points from the window's first on and
+    read the two blocks holding it back from LDS, k = 64 updates the two
+    blocks in place.  Ragged sectors around 64-point blocks up to 4096
+    points, so that windows start at every offset of a block and run into
+    the sector's ends, k from 1 to 64, every reading, the 16-wave kernel and
+    the light one, graph replays: every index against the oracle."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(77)
+    sizes = [1, 2, 63, 64, 65, 127, 129, 191, 700, 1023, 2049, 4031, 4095, 4096, 3000, 257]
+    ks = [1, 2, 31, 32, 33, 62, 63, 64, 7, 16, 40, 63, 64, 32, 1, 64]
+    flags = [i % 8 for i in range(len(sizes))]
+    cs = [max(1, n // 3) for n in sizes]
+    starts = [int(rng.integers(0, n)) for n in sizes]
+    clouds = [synth.object_cloud(n, seed=100 + i) if n >= 64 else synth.uniform_cube(n, seed=100 + i)
+              for i, n in enumerate(sizes)]
+    B.tune_reset()
+    try:
+        B.set_pool_policy(shape[0], shape[1], False, 0)
+        B.tune_npdu(4096, 64, False)   # sectors of at most 4096 points with k <= 64: coordinates from L2
+        plan = _batch_case(B, torch, dev, clouds, cs, [1] * len(sizes), ks, starts, graph_replays=2, flags=flags)
+        assert (plan.pool_waves, plan.pool_groups) == shape
+    finally:
+        B.tune_reset()
+
+
 @pytest.mark.parametrize("shape", [(4, 1), (8, 1), (4, 2), (12, 1), (16, 1), (12, 2), (16, 2)])
 @pytest.mark.parametrize("seeding", [(False, 0), (True, 3)])
 def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
