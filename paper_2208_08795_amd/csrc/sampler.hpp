@@ -588,7 +588,8 @@ __device__ __forceinline__ void sample_sector_npdu_narrow_l2(const float* __rest
         // the sample's coordinates: scalar loads (the points are read-only
         // while the kernel runs, so the constant address space holds)
         typedef const __attribute__((address_space(4))) float* ConstPtr;
-        const ConstPtr p = (ConstPtr)xyz + 3 * cur;
+        typedef const __attribute__((address_space(4))) char* ConstBytes;
+        const ConstPtr p = (ConstPtr)((ConstBytes)xyz + (uint32_t)(12 * cur));   // a 32-bit byte offset
         const float px = p[0], py = p[1], pz = p[2];
         int lo, hi;
         if constexpr (SHIFT) {   // kNpduShiftEdges: keep the window's size inside the sector
