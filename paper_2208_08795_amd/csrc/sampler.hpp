@@ -1056,9 +1056,11 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
             py = __uint_as_float(rec[4 * cur + 2]);
             pz = __uint_as_float(rec[4 * cur + 3]);
         } else {
-            // a 32-bit byte offset: one scalar load with an offset register
-            const float* const p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(xyz) +
-                                                                  (uint32_t)(12 * cur));
+            // scalar loads at a 32-bit byte offset (the points are read-only
+            // while the kernel runs, so the constant address space holds)
+            typedef const __attribute__((address_space(4))) float* ConstPtr;
+            typedef const __attribute__((address_space(4))) char* ConstBytes;
+            const ConstPtr p = (ConstPtr)((ConstBytes)xyz + (uint32_t)(12 * cur));
             px = p[0];
             py = p[1];
             pz = p[2];
