@@ -656,6 +656,75 @@ def test_pool_policies_stay_exact(B, torch_dev, shape, seeding):
         B.tune_reset()
 
 
+@pytest.mark.parametrize("policy", ["builtin", "l2_16", "lite_12x2", "regs_8", "l2_12"])
+def test_pooled_random_batches_every_policy(B, torch_dev, policy):
+    """Random batches (seeded) under every pooled policy the tuner can
+    install: cloud sizes log-uniform in [1, 32768], 1 to 16 sectors, k from 0
+    to 200 or plain AFPS, every reading, random starts and sample counts; one
+    eager launch against the oracle, and (NPDU-only plans) a launch of three
+    rounds equal to it."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(1234 + ["builtin", "l2_16", "lite_12x2", "regs_8", "l2_12"].index(policy))
+    lite = policy == "lite_12x2"
+    B.tune_reset()
+    try:
+        if policy == "l2_16":
+            B.set_pool_policy(16, 1, False, 0)
+            B.tune_npdu(4096, 64, False)
+        elif policy == "l2_12":
+            B.set_pool_policy(12, 1, True, 3)
+            B.tune_npdu(8192, 1 << 30, False)
+        elif policy == "lite_12x2":
+            B.set_pool_policy(12, 2, False, 0)
+            B.tune_npdu(4096, 64, False)
+        elif policy == "regs_8":
+            B.set_pool_policy(8, 1, True, 3)
+            B.tune_npdu(4096, 64, False)
+        for trial in range(3):
+            sizes, ms, ks, cs, starts, flags = [], [], [], [], [], []
+            for _ in range(int(rng.integers(5, 30))):
+                n = int(np.exp(rng.uniform(0, np.log(32768))))
+                m = int(rng.integers(1, min(16, n) + 1))
+                if lite:
+                    m = max(m, (n + 4095) // 4096)
+                    k = int(rng.choice([0, 1, 7, 31, 32, 33, 63, 64]))
+                else:
+                    k = [None, 0, 1, 7, 31, 32, 33, 63, 64, 65, 100, 200][int(rng.integers(0, 12))]
+                    if k is None and n > 8192:
+                        k = 32
+                c = int(rng.integers(m, min(n, 4096 if k is None else n) + 1))
+                fl = int(rng.integers(0, 8)) if k is not None else 0
+                if k == 0:
+                    fl &= 3   # k counting the sample needs k >= 1
+                sizes.append(n)
+                ms.append(m)
+                ks.append(k)
+                cs.append(c)
+                starts.append(int(rng.integers(0, n)))
+                flags.append(fl)
+            clouds = [synth.object_cloud(n, seed=100 * trial + i) if n >= 64 else synth.uniform_cube(n, seed=100 * trial + i)
+                      for i, n in enumerate(sizes)]
+            print("policy %s trial %d: %d clouds, %d points" % (policy, trial, len(sizes), sum(sizes)), flush=True)
+            plan = B.BatchPlan(sizes, cs, ms, ks, starts, device=dev, flags=flags)
+            xyz = torch.from_numpy(np.concatenate(clouds).astype(np.float32)).to(dev)
+            out = plan.launch(xyz)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            for i, p in enumerate(clouds):
+                o = plan.descs[i].out_offset
+                want = oracle.afps(p, cs[i], ms[i], ks[i], starts[i], flags=flags[i])
+                assert np.array_equal(got[o:o + cs[i]], want), "trial %d cloud %d" % (trial, i)
+            if all(k is not None for k in ks):
+                outs = [torch.full_like(out, -7) for _ in range(3)]
+                plan.launch_rounds([(xyz, o) for o in outs])
+                torch.cuda.synchronize()
+                plan.status()
+                assert all(torch.equal(o, out) for o in outs)
+            plan.close()
+    finally:
+        B.tune_reset()
+
+
 def test_npdu_tuner_choices_stay_exact(B, torch_dev):
     """The NPDU tuner times every pooled launch shape, coordinate placement
     and seeding policy on a batch (one launch of several rounds each), checks
