@@ -13,7 +13,10 @@
  *
  * Common conventions
  *   xyz      DEVICE pointer to n points, row-major fp32 (x, y, z per point,
- *            12 bytes per point, 4-byte aligned).  Read only.
+ *            12 bytes per point, 4-byte aligned).  Read only, and not to be
+ *            written while a launch that reads it runs (kernels read the
+ *            points partly through the scalar data cache, which a concurrent
+ *            write would not update).
  *   out_idx  DEVICE pointer to c int32 entries, written with indices into the
  *            cloud (0 .. n-1): sector-major, and within a sector in pick order.
  *   stream   a hipStream_t passed as void* (NULL = the default stream).  Every
