@@ -1009,6 +1009,18 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
         }
     }
 
+    // The maxima of blocks b0, b0 + 1 holding d0, d1, recorded; returns the
+    // larger.  Block b0+1 may be the padding block (maximum 0, never the
+    // lowest holder of a maximum); past the registers it is not recorded.
+    auto reduce_pair = [&](int b0, uint32_t d0, uint32_t d1) {
+        uint32_t g0, g1;
+        wave_max2(d0, d1, g0, g1);
+        const uint32_t i0 = (uint32_t)__builtin_ctzll(ballot(d0 == g0));
+        const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
+        set_pair(b0, g0, i0, g1, i1);
+        return max(g0, g1);
+    };
+
     // Update and re-reduce the two blocks b0, b0 + 1 (window points [lo, hi]
     // only); returns the larger block maximum.
     auto update_pair = [&](int b0, int lo, int span, float px, float py, float pz) {
@@ -1037,18 +1049,25 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
         const uint32_t d1 = (uint32_t)(j1 - lo) <= (uint32_t)span ? e1 : b_d;
         rec[kWords * j0] = d0;
         rec[kWords * j1] = d1;
-        uint32_t g0, g1;
-        wave_max2(d0, d1, g0, g1);
-        const uint32_t i0 = (uint32_t)__builtin_ctzll(ballot(d0 == g0));
-        const uint32_t i1 = (uint32_t)__builtin_ctzll(ballot(d1 == g1));
-        // Block b0+1 may be the padding block (maximum 0, never the lowest
-        // holder of a maximum); past the registers it is not recorded.
-        set_pair(b0, g0, i0, g1, i1);
-        return max(g0, g1);
+        return reduce_pair(b0, d0, d1);
+    };
+    // Coordinates from L2 and a window of at most 64 points (k <= 63) in
+    // blocks b0, b0 + 1 with b0 = lo >> 6: lane l takes point lo + l (one
+    // load, one update, written to LDS) and the two blocks are read back.
+    auto update_window = [&](int b0, int lo, int span, float px, float py, float pz) {
+        const v3u32 P = __builtin_amdgcn_raw_buffer_load_b96(xyz_rsrc, 12 * lo + lane12, 0, 0);
+        uint32_t* const ww = rec + lo + lane;   // inside the padded sector: lo + 63 < n + 64
+        const uint32_t dw = ww[0];
+        const uint32_t ew = min(dw, sq_dist_bits(__uint_as_float(P.x), __uint_as_float(P.y), __uint_as_float(P.z),
+                                                 px, py, pz));
+        ww[0] = lane <= span ? ew : dw;
+        const int j0 = 64 * b0 + lane;
+        return reduce_pair(b0, rec[j0], rec[j0 + 64]);
     };
 
     // One iteration; NARROW (k <= 64: the window lies in two adjacent blocks)
-    // fixes the number of block pairs at one.
+    // fixes the number of block pairs at one; its value 2 (coordinates from
+    // L2, k <= 63) updates the window's own 64 lanes.
     auto step = [&](int s, auto narrow) {
         float px, py, pz;
         if constexpr (XYZ_IN_LDS) {
@@ -1089,7 +1108,10 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
 #pragma unroll
         for (int r = 0; r < R; ++r) mo = max(mo, (uint32_t)(64 * r + lane - blo) >= (uint32_t)(2 * pairs) ? bm[r] : 0u);
         uint32_t best = wave_max(mo);
-        best = max(best, update_pair(blo, lo, hi - lo, px, py, pz));
+        if constexpr (decltype(narrow)::value == 2)
+            best = max(best, update_window(blo, lo, hi - lo, px, py, pz));
+        else
+            best = max(best, update_pair(blo, lo, hi - lo, px, py, pz));
         if constexpr (!decltype(narrow)::value)
             for (int p = 1; p < pairs; ++p) best = max(best, update_pair(blo + 2 * p, lo, hi - lo, px, py, pz));
         cur = lowest_with(best);
@@ -1108,8 +1130,14 @@ __device__ __forceinline__ void sample_sector_npdu_blocks(const float* __restric
             if (lane < s_end) out[i0 + lane] = (int32_t)(picks + (uint32_t)base);
         }
     };
-    if (k <= 64) run(std::integral_constant<bool, true>{});
-    else run(std::integral_constant<bool, false>{});
+    if constexpr (!XYZ_IN_LDS) {
+        if (k <= 63) {
+            run(std::integral_constant<int, 2>{});
+            return;
+        }
+    }
+    if (k <= 64) run(std::integral_constant<int, 1>{});
+    else run(std::integral_constant<int, 0>{});
 }
 
 // NPDU on one sector (Sec. III-C), one wave.
